@@ -1,0 +1,288 @@
+"""Checks that pin the FP64 oracle to facts outside itself.
+
+Each ``check_*`` raises AssertionError when the oracle disagrees with what the
+paper or the mathematics fixes. ``test_oracle_pins.py`` runs them on the real
+oracle; ``test_oracle_mutants.py`` plants plausible mistakes in the oracle
+and asserts that some check fails for each.
+"""
+
+import math
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import torch
+
+import oracle
+import oracle.scalar
+import oracle.tmlp as T
+import synth
+
+
+def tiny_model(seed, L, W, tails="mult", scale="plain"):
+    return oracle.parse_blob(synth.write_blob(
+        synth.siren_tmlp(seed, L, W, tails=tails, scale=scale)))
+
+
+# -- cell rule ---------------------------------------------------------------
+
+def edge_coordinates(R):
+    """FP32 coordinates on, beside and beyond every cell face of an R-map."""
+    vals = [0.0, -0.0, 1.0, -1.0, 1e-30, -1e-30, 1.5, -1.5, 3e38, -3e38,
+            float("inf"), float("-inf"), float("nan")]
+    for i in range(R + 1):
+        f = np.float32(-1.0 + 2.0 * i / R)
+        vals += [float(f), float(np.nextafter(f, np.float32(2))),
+                 float(np.nextafter(f, np.float32(-2)))]
+    rng = np.random.Generator(np.random.PCG64(7))
+    vals += list(rng.uniform(-1.1, 1.1, size=200).astype(np.float32))
+    return np.array(vals, dtype=np.float32)
+
+
+def cell_by_rational_box(x, R):
+    """Cell of one coordinate by exact half-open interval membership."""
+    if math.isnan(x):
+        return 0
+    if x == float("inf"):
+        return R - 1
+    if x == float("-inf"):
+        return 0
+    q = Fraction(float(x))
+    for i in range(R):
+        lo = Fraction(-1) + Fraction(2 * i, R)
+        hi = Fraction(-1) + Fraction(2 * (i + 1), R)
+        if lo <= q < hi:
+            return i
+    return 0 if q < -1 else R - 1
+
+
+def check_cell_rule(R):
+    xs = edge_coordinates(R)
+    pts = np.stack([xs, xs[::-1], np.roll(xs, 5)], axis=1)
+    got = T.voxel_index(pts, R)
+    for a in range(3):
+        want = [cell_by_rational_box(float(v), R) for v in pts[:, a]]
+        assert np.array_equal(got[:, a], want), f"cell rule wrong for R={R}"
+
+
+# -- forward pass --------------------------------------------------------------
+
+def torch_textbook_mlp(model):
+    """Eq. 1 MLP from torch.nn layers: Linear/sin stack + a Linear output.
+
+    Uses the model's hidden layers and its last tail (which must be linear)
+    as the output layer; intermediate tails play no part.
+    """
+    L, W = model["L"], model["W"]
+    layers = []
+    for j in range(L):
+        fan_in = 3 if j == 0 else W
+        lin = torch.nn.Linear(fan_in, W, dtype=torch.float64)
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(model["W_"][j]))
+            lin.bias.copy_(torch.from_numpy(model["b_"][j]))
+        layers.append((lin, model["omega"][j]))
+    kind, a, c = model["tails"][L - 1]
+    assert kind == "linear"
+    out = torch.nn.Linear(W, 1, dtype=torch.float64)
+    with torch.no_grad():
+        out.weight.copy_(torch.from_numpy(a)[None, :])
+        out.bias.fill_(float(c))
+
+    def f(x):
+        h = x
+        for lin, om in layers:
+            h = torch.sin(om * lin(h))
+        return out(h)[:, 0]
+    return f
+
+
+def with_zeroed_intermediate_tails(model):
+    m = dict(model)
+    tails = []
+    for i, t in enumerate(model["tails"]):
+        if i < model["L"] - 1:
+            z = np.zeros(model["W"])
+            tails.append(("linear", z, 0.0) if t[0] == "linear" else ("mult", z, 0.0, z, 0.0))
+        else:
+            tails.append(("linear", t[1], t[2]) if t[0] == "linear" else None)
+    m["tails"] = tails
+    return m
+
+
+def check_textbook_mlp(seed=3, L=4, W=16, n=300):
+    model = with_zeroed_intermediate_tails(tiny_model(seed, L, W, tails="linear"))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    want = torch_textbook_mlp(model)(torch.from_numpy(x)).detach().numpy()
+    got = T.forward(model, x, np.full(n, L))
+    assert np.allclose(got, want, rtol=0, atol=1e-12), "textbook MLP reduction"
+
+
+def check_quadratic_form(seed=5, W=24, n=50):
+    """Appendix: (a.h + c)(b.h + d) = h^T Q h + u^T h + s,
+    Q = a b^T, u = d a + c b, s = c d."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a, b = rng.normal(size=W), rng.normal(size=W)
+    c, d = rng.normal(), rng.normal()
+    h = rng.uniform(-1, 1, size=(n, W))
+    Q = np.outer(a, b)
+    u = d * a + c * b
+    s = c * d
+    want = np.einsum("ni,ij,nj->n", h, Q, h) + h @ u + s
+    got = T._tail(("mult", a, c, b, d), h)
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12), "quadratic form"
+
+
+def truncated(model, k):
+    return {"L": k, "W": model["W"], "omega": model["omega"][:k],
+            "W_": model["W_"][:k], "b_": model["b_"][:k], "tails": model["tails"][:k]}
+
+
+def check_truncation(seed=11, L=5, W=12, n=200):
+    model = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    d = rng.integers(1, L + 1, size=n)
+    got = T.forward(model, x, d)
+    for k in range(1, L + 1):
+        sel = d == k
+        want = T.forward(truncated(model, k), x[sel], np.full(sel.sum(), k))
+        assert np.allclose(got[sel], want, rtol=0, atol=1e-13), f"exit at {k}"
+    allt = T.forward_all_tails(model, x)
+    assert np.allclose(got, allt[np.arange(n), d - 1], rtol=0, atol=1e-13)
+
+
+def check_accumulation(seed=13, L=5, W=12, n=100):
+    """Only tail k non-zero: y_d = 0 for d < k and y_d = t_k for every d >= k."""
+    base = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    for k in range(1, L + 1):
+        m = dict(base)
+        z = np.zeros(W)
+        m["tails"] = [t if i == k - 1 else ("linear", z, 0.0)
+                      for i, t in enumerate(base["tails"])]
+        ys = [T.forward(m, x, np.full(n, d)) for d in range(1, L + 1)]
+        for d in range(1, k):
+            assert np.all(ys[d - 1] == 0.0), "tail contributes before its layer"
+        tk = [oracle.scalar.forward_point(m, x[i], k) for i in range(5)]
+        for d in range(k, L + 1):
+            assert np.allclose(ys[d - 1], ys[k - 1], rtol=0, atol=0), "not cumulative"
+        assert np.allclose(ys[k - 1][:5], tk, rtol=0, atol=1e-13)
+        assert np.any(ys[k - 1] != 0.0)
+
+
+def check_scalar_twin(seed=17, L=3, W=8):
+    model = tiny_model(seed, L, W)
+    x = synth.grid_points(8).astype(np.float64)
+    d = (np.arange(x.shape[0]) % L) + 1
+    got = T.forward(model, x, d)
+    want = np.array([oracle.scalar.forward_point(model, x[i], int(d[i]))
+                     for i in range(x.shape[0])])
+    assert np.allclose(got, want, rtol=0, atol=1e-12), "scalar twin"
+
+
+def check_mpmath(seed=19, L=2, W=6, n=10):
+    """Closed form at 50 digits: y_2 = sum of both tails of a 2-layer net."""
+    model = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    got = T.forward(model, x, np.full(n, L))
+    mpmath.mp.dps = 50
+    mp = mpmath.mpf
+    for i in range(n):
+        h = [mp(float(v)) for v in x[i]]
+        y = mp(0)
+        for j in range(L):
+            Wj, bj, om = model["W_"][j], model["b_"][j], mp(model["omega"][j])
+            h = [mpmath.sin(om * (mpmath.fsum(mp(float(Wj[u, k])) * h[k] for k in range(len(h)))
+                                  + mp(float(bj[u])))) for u in range(W)]
+            t = model["tails"][j]
+            dot = lambda v: mpmath.fsum(mp(float(v[k])) * h[k] for k in range(W))
+            if t[0] == "linear":
+                y += dot(t[1]) + mp(float(t[2]))
+            else:
+                y += (dot(t[1]) + mp(float(t[2]))) * (dot(t[3]) + mp(float(t[4])))
+        assert abs(float(y) - got[i]) < 1e-13, "mpmath spot value"
+
+
+def check_lod_and_far(seed=23, L=4, W=8, R=8):
+    model = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dmap = rng.integers(0, L + 1, size=(R, R, R)).astype(np.uint8)
+    far = rng.normal(size=(R, R, R)).astype(np.float32)
+    x = synth.grid_points(16).astype(np.float64)
+    d = T.lookup_depth(x, dmap, L)
+    i = T.voxel_index(x, R)
+    assert np.array_equal(d, dmap[i[:, 0], i[:, 1], i[:, 2]])
+    y = T.forward(model, x, d, far=far)
+    zero = d == 0
+    assert np.array_equal(y[zero], far[i[zero, 0], i[zero, 1], i[zero, 2]].astype(np.float64))
+    allt = T.forward_all_tails(model, x)
+    for m in range(1, L + 1):
+        dm = T.lookup_depth(x, dmap, L, max_depth=m)
+        assert np.array_equal(dm, np.minimum(d, m))
+        ym = T.forward(model, x, dm, far=far)
+        nz = dm > 0
+        assert np.allclose(ym[nz], allt[nz, dm[nz] - 1], rtol=0, atol=1e-13)
+    full = T.lookup_depth(x, dmap, L, mode=T.MODE_FULL)
+    assert np.all(full == L)
+    allL = np.full((R, R, R), L, dtype=np.uint8)
+    assert np.array_equal(T.lookup_depth(x, allL, L), full)
+    assert np.allclose(T.forward(model, x, full), allt[:, L - 1], rtol=0, atol=1e-13)
+
+
+# -- gradient ------------------------------------------------------------------
+
+def torch_tmlp(model):
+    Ws = [torch.from_numpy(w) for w in model["W_"]]
+    bs = [torch.from_numpy(b) for b in model["b_"]]
+
+    def f(x, k):
+        h, y = x, torch.zeros(x.shape[0], dtype=torch.float64)
+        for j in range(k):
+            h = torch.sin(model["omega"][j] * (h @ Ws[j].T + bs[j]))
+            t = model["tails"][j]
+            if t[0] == "linear":
+                y = y + h @ torch.from_numpy(t[1]) + t[2]
+            else:
+                y = y + (h @ torch.from_numpy(t[1]) + t[2]) * (h @ torch.from_numpy(t[3]) + t[4])
+        return y
+    return f
+
+
+def check_gradient_autograd(seed=29, L=4, W=16, n=120):
+    model = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    d = rng.integers(1, L + 1, size=n)
+    got = T.gradient(model, x, d)
+    f = torch_tmlp(model)
+    for k in range(1, L + 1):
+        sel = np.nonzero(d == k)[0]
+        xt = torch.from_numpy(x[sel]).requires_grad_(True)
+        f(xt, k).sum().backward()
+        assert np.allclose(got[sel], xt.grad.numpy(), rtol=1e-10, atol=1e-10), f"grad depth {k}"
+
+
+def check_gradient_fd(seed=31, L=3, W=10, n=60, h=1e-6):
+    model = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    d = rng.integers(1, L + 1, size=n)
+    got = T.gradient(model, x, d)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd = (T.forward(model, x + e, d) - T.forward(model, x - e, d)) / (2 * h)
+        scale = 1.0 + np.abs(got[:, a])
+        assert np.all(np.abs(fd - got[:, a]) <= 1e-6 * scale), "central difference"
+
+
+ALL_CHECKS = [
+    lambda: [check_cell_rule(R) for R in (2, 4, 32, 128)],
+    check_textbook_mlp, check_quadratic_form, check_truncation,
+    check_accumulation, check_scalar_twin, check_mpmath, check_lod_and_far,
+    check_gradient_autograd, check_gradient_fd,
+]
