@@ -1,0 +1,207 @@
+/*
+ * sand.h -- C ABI of the SAND query library for AMD Instinct MI355X (gfx950).
+ *
+ * SAND answers signed-distance queries with a tailed MLP (T-MLP) whose
+ * evaluation depth varies per point (Sec. 3, overview figure): a dense
+ * network-depth map gives each point its exit depth d(x) (Sec. 3.2), the
+ * T-MLP runs hidden layers 1..d(x) only, and the answer is the accumulated
+ * tail output y_d = t_1 + ... + t_d (Eq. 2), with tails 2..L optionally the
+ * product of two linear heads (Eq. 3). A depth of 0 marks a far-field cell
+ * whose stored value is returned without running the network (Eq. 7,
+ * Sec. 3.4). Capping the depth gives the level-of-detail control of Sec. 3.4.
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented "device" must point to memory on the model's GPU;
+ *    "host" pointers to ordinary CPU memory. The caller owns every buffer it
+ *    passes and the library never frees or keeps them past the call (except
+ *    where a server entry point says otherwise).
+ *  - All argument and format checks happen on the host before anything is
+ *    enqueued; a failing check returns a status != SAND_OK and touches
+ *    neither the device nor the output buffers. sand_last_error() then holds
+ *    a message for the calling thread.
+ *  - Query entry points are asynchronous and ordered on the given HIP
+ *    stream (a hipStream_t passed as void*, NULL = the null stream). Model
+ *    and map handles are immutable after creation and may be used by
+ *    several streams and threads at once; free them only after their work
+ *    has completed.
+ *  - Device-side failures (a failed launch or allocation) surface as
+ *    SAND_ERR_DEVICE from the call that observed them.
+ */
+#ifndef SAND_H_
+#define SAND_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sand_model_s* sand_model;
+typedef struct sand_depthmap_s* sand_depthmap;
+typedef struct sand_server_s* sand_server;
+
+typedef enum {
+  SAND_OK = 0,
+  SAND_ERR_INVALID = 1,     /* bad argument (null pointer, size, enum value) */
+  SAND_ERR_FORMAT = 2,      /* malformed model blob or depth map */
+  SAND_ERR_NOMEM = 3,       /* device or host allocation failed */
+  SAND_ERR_DEVICE = 4,      /* HIP runtime or launch error */
+  SAND_ERR_BUDGET = 5,      /* a server request alone exceeds the HBM budget */
+  SAND_ERR_UNSUPPORTED = 6, /* valid input outside what this build supports */
+  SAND_ERR_TIMEOUT = 7      /* sand_server_wait gave up before completion */
+} sand_status;
+
+/* Arithmetic of the hidden-layer products W_j h_{j-1}, j >= 2. Layer 1
+ * (its omega-scaled sine argument), the sines and every tail are FP32 in
+ * all three; the hidden products accumulate in FP32. */
+typedef enum { SAND_FP32 = 0, SAND_BF16 = 1, SAND_FP16 = 2 } sand_precision;
+
+/* Where the exit depth comes from:
+ *  ADAPTIVE: the depth map (Sec. 3.4);
+ *  FULL:     every point runs all L layers (the plain full-depth network);
+ *  FORCED:   a caller-given depth per point (opts.forced_depth). */
+typedef enum { SAND_ADAPTIVE = 0, SAND_FULL = 1, SAND_FORCED = 2 } sand_mode;
+
+typedef struct {
+  int32_t precision;            /* sand_precision */
+  int32_t mode;                 /* sand_mode */
+  int32_t max_depth;            /* > 0: exit depth <- min(depth, max_depth)
+                                   (level of detail, Sec. 3.4); 0: no clamp */
+  int32_t reserved;             /* must be 0 */
+  const uint8_t* forced_depth;  /* device [n], FORCED only: values 0..L
+                                   (0 needs a map with far-field values) */
+  uint8_t* depth_out;           /* device [n] or NULL: receives each
+                                   point's exit depth */
+  void* workspace;              /* device scratch or NULL (then the library
+                                   allocates stream-ordered scratch itself) */
+  size_t workspace_bytes;       /* size of workspace; must be at least
+                                   sand_query_workspace_size(n) when given */
+} sand_query_opts;
+
+/* Fill opts with the defaults: FP32, ADAPTIVE, no clamp, no buffers. */
+void sand_query_opts_init(sand_query_opts* opts);
+
+/* ---- models ------------------------------------------------------------ */
+
+/* Parse a version-1 model blob (host memory, nbytes long) and upload it to
+ * GPU `device`, packed for every precision.
+ *
+ * Blob layout (little-endian): 64-byte header = magic "SANDTMLP", u32
+ * version (1), u32 L (1..16 hidden sine layers), u32 W (1..352 hidden
+ * width), u32 input dim (3), f32 omega of layer 1, f32 omega of layers
+ * 2..L, u8[16] tail kind per layer (0 linear, 1 multiplicative; unused
+ * entries 0), 16 zero bytes; then float32 W_1 [W x 3], b_1 [W],
+ * (W_j [W x W] row-major out x in, b_j [W]) for j = 2..L, and per tail in
+ * layer order a [W], c (linear) or a0 [W], c0, a1 [W], c1 (Eq. 3).
+ * Layer j computes h_j = sin(omega_j (W_j h_{j-1} + b_j)).
+ *
+ * Errors: SAND_ERR_INVALID (null blob/out, bad device), SAND_ERR_FORMAT
+ * (magic, version, size or a non-finite parameter), SAND_ERR_UNSUPPORTED
+ * (W > 352), SAND_ERR_NOMEM / SAND_ERR_DEVICE. On success *out owns the
+ * device copy until sand_free_model. */
+sand_status sand_load_model(const void* blob, size_t nbytes, int device,
+                            sand_model* out);
+void sand_free_model(sand_model model);
+/* Number of hidden layers and width of a loaded model. */
+sand_status sand_model_info(sand_model model, int32_t* n_layers,
+                            int32_t* width);
+
+/* ---- depth maps ---------------------------------------------------------- */
+
+/* Upload a dense R^3 network-depth map (the dense stand-in for the octree
+ * of Sec. 3.2) for use with `model`.
+ *  depth_host: host uint8 [R][R][R], C order (x slowest, z fastest), values
+ *              0..L; cell i along an axis covers [-1 + 2i/R, -1 + 2(i+1)/R).
+ *  R:          power of two, 2..1024.
+ *  far_host:   host float32 [R][R][R] far-field values (Eq. 7), read for
+ *              cells of depth 0; may be NULL only if no cell has depth 0.
+ * Points outside [-1, 1]^3 use the border cell; a NaN coordinate uses
+ * cell 0 on that axis.
+ * Errors: SAND_ERR_INVALID (null pointers, bad R), SAND_ERR_FORMAT (a
+ * value > L, depth 0 without far values), SAND_ERR_NOMEM/_DEVICE. */
+sand_status sand_build_depthmap(sand_model model, const uint8_t* depth_host,
+                                int32_t R, const float* far_host,
+                                sand_depthmap* out);
+void sand_free_depthmap(sand_depthmap map);
+
+/* ---- queries ------------------------------------------------------------- */
+
+/* Bytes of device scratch a query of n points needs (same for the gradient). */
+size_t sand_query_workspace_size(int64_t n);
+
+/* Signed distance of n points (Sec. 3.4 inference).
+ *  xyz_dev: device float32 [n][3] (x, y, z per point), 4-byte aligned.
+ *  sdf_dev: device float32 [n], written with y_{d(x)} (or the far value).
+ *  map:     required for ADAPTIVE and for FORCED depths of 0; ignored by
+ *           FULL (may be NULL there).
+ *  opts:    NULL = defaults.
+ * n = 0 is a no-op. Errors: SAND_ERR_INVALID (null pointers, n < 0 or
+ * n > 2^31 - 1, bad enum, map of another model, workspace too small). */
+sand_status sand_query(sand_model model, sand_depthmap map,
+                       const float* xyz_dev, int64_t n, float* sdf_dev,
+                       const sand_query_opts* opts, void* hip_stream);
+
+/* Input gradient (surface normal direction) of the queried value with each
+ * point's exit depth held fixed: grad_dev[i] = dy[i] * d y_{d(x_i)} / d x_i,
+ * computed by reverse accumulation from the exit tail back through layers
+ * d..1 (derived from Eq. 2-3). Far-field points (depth 0) get 0.
+ *  dy_dev:   device float32 [n] upstream gradient, or NULL for all ones.
+ *  sdf_dev:  device float32 [n] or NULL; receives the forward values.
+ *  grad_dev: device float32 [n][3].
+ * Other arguments and errors as sand_query. */
+sand_status sand_query_grad(sand_model model, sand_depthmap map,
+                            const float* xyz_dev, int64_t n,
+                            const float* dy_dev, float* sdf_dev,
+                            float* grad_dev, const sand_query_opts* opts,
+                            void* hip_stream);
+
+/* ---- serving --------------------------------------------------------------- */
+
+typedef struct {
+  double t_submit;     /* seconds, library monotonic clock */
+  double t_admit;      /* admitted under the HBM budget */
+  double t_launch;     /* its batch was enqueued */
+  double t_done;       /* its results were complete on the device */
+  double t_copied;     /* its results were in the caller's host buffer */
+  int64_t n;           /* points in the request */
+  int32_t batch_size;  /* requests that shared its launches */
+  int32_t reserved;
+} sand_req_stats;
+
+/* A request loop on one GPU. Requests name a resident model and map and
+ * carry a host query set; the server admits them while the bytes they need
+ * (points, results, scratch) fit `hbm_budget_bytes`, packs the admitted
+ * requests of all models into shared launches (continuous batching: requests
+ * arriving while others run join the next launch), overlaps launches on
+ * `n_streams` streams and copies results back. Precision as in
+ * sand_query_opts (FP32, BF16 or FP16); mode is always ADAPTIVE.
+ * A result is the same whether a request runs alone or batched. */
+sand_status sand_server_create(int device, size_t hbm_budget_bytes,
+                               int32_t precision, int32_t n_streams,
+                               sand_server* out);
+/* Queue one request; never blocks. xyz_host: host float32 [n][3]; sdf_host:
+ * host float32 [n] that receives the results. Both must stay valid until
+ * sand_server_wait returns for this ticket. Errors: SAND_ERR_INVALID,
+ * SAND_ERR_BUDGET (the request alone exceeds the budget). */
+sand_status sand_server_submit(sand_server server, sand_model model,
+                               sand_depthmap map, const float* xyz_host,
+                               int64_t n, float* sdf_host, uint64_t* ticket);
+/* Block until request `ticket` has completed (timeout_s < 0: no limit).
+ * stats may be NULL. Each ticket can be waited for once. */
+sand_status sand_server_wait(sand_server server, uint64_t ticket,
+                             double timeout_s, sand_req_stats* stats);
+/* Stop accepting requests, finish the admitted ones and free everything. */
+void sand_server_destroy(sand_server server);
+
+/* ---- errors -------------------------------------------------------------- */
+
+const char* sand_status_str(sand_status status);
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char* sand_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAND_H_ */

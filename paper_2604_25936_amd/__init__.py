@@ -1,0 +1,13 @@
+"""SAND query path for AMD Instinct MI355X (gfx950).
+
+Batched signed-distance queries of a tailed sine MLP (T-MLP) whose depth
+varies per point through a network-depth map (Sec. 3 of the SAND paper),
+served by hand-written HIP kernels behind the C ABI of include/sand.h.
+This package is the Python binding of that library.
+"""
+
+from .sand import (Model, DepthMap, SandError, load_model, build_depthmap, query,
+                   query_grad, query_workspace_size, library, PRECISIONS, MODES)
+
+__all__ = ["Model", "DepthMap", "SandError", "load_model", "build_depthmap", "query",
+           "query_grad", "query_workspace_size", "library", "PRECISIONS", "MODES"]

@@ -1,0 +1,532 @@
+// C ABI of the SAND query library: model loading and packing, depth maps,
+// and the query entry points (argument checks, scratch, launch sequence).
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sand.h"
+#include "sand_internal.h"
+#include "sand_host.h"
+
+using namespace sand;
+
+// ---------------------------------------------------------------- errors --
+
+namespace sand {
+
+static thread_local std::string g_last_error;
+
+sand_status fail(sand_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+sand_status device_fail(hipError_t e, const char* what) {
+  return fail(SAND_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+  ok = hipGetDevice(&prev) == hipSuccess;
+  if (ok && prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+}
+DeviceGuard::~DeviceGuard() {
+  int cur = -1;
+  if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+}
+
+}  // namespace sand
+
+extern "C" const char* sand_status_str(sand_status s) {
+  switch (s) {
+    case SAND_OK: return "ok";
+    case SAND_ERR_INVALID: return "invalid argument";
+    case SAND_ERR_FORMAT: return "malformed model or map";
+    case SAND_ERR_NOMEM: return "out of memory";
+    case SAND_ERR_DEVICE: return "device error";
+    case SAND_ERR_BUDGET: return "request exceeds the memory budget";
+    case SAND_ERR_UNSUPPORTED: return "unsupported";
+    case SAND_ERR_TIMEOUT: return "timed out";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* sand_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void sand_query_opts_init(sand_query_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SAND_FP32;
+  o->mode = SAND_ADAPTIVE;
+}
+
+// ---------------------------------------------------------------- models --
+
+namespace {
+
+struct Blob {
+  int L = 0, W = 0;
+  float om[2] = {0, 0};
+  uint8_t kind[kMaxLayers] = {};
+  std::vector<const float*> Wm, b;      // per layer
+  std::vector<const float*> a0, a1;     // per tail (a1 null for linear)
+  std::vector<float> c0, c1;            // per tail (c1 = 1 for linear)
+};
+
+uint32_t rd32(const unsigned char* p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+sand_status parse_blob(const void* data, size_t nbytes, Blob& B, std::vector<float>& store) {
+  const unsigned char* p = (const unsigned char*)data;
+  if (nbytes < 64 || std::memcmp(p, "SANDTMLP", 8) != 0)
+    return fail(SAND_ERR_FORMAT, "model blob: bad magic or shorter than the 64-byte header");
+  const uint32_t version = rd32(p + 8), L = rd32(p + 12), W = rd32(p + 16), din = rd32(p + 20);
+  if (version != 1) return fail(SAND_ERR_FORMAT, "model blob: version %u, expected 1", version);
+  if (din != 3) return fail(SAND_ERR_FORMAT, "model blob: input dimension %u, expected 3", din);
+  if (L < 1 || L > (uint32_t)kMaxLayers)
+    return fail(SAND_ERR_FORMAT, "model blob: %u layers, expected 1..%d", L, kMaxLayers);
+  if (W < 1) return fail(SAND_ERR_FORMAT, "model blob: width 0");
+  if (W > (uint32_t)kMaxWidth)
+    return fail(SAND_ERR_UNSUPPORTED, "model blob: width %u exceeds %d", W, kMaxWidth);
+  for (int i = 0; i < 16; ++i) {
+    const uint8_t k = p[32 + i];
+    if ((uint32_t)i < L ? (k > 1) : (k != 0))
+      return fail(SAND_ERR_FORMAT, "model blob: bad tail kind %u at layer %d", k, i + 1);
+  }
+  for (int i = 48; i < 64; ++i)
+    if (p[i] != 0) return fail(SAND_ERR_FORMAT, "model blob: reserved header bytes not zero");
+  size_t nf = (size_t)W * 3 + W + (size_t)(L - 1) * ((size_t)W * W + W);
+  for (uint32_t i = 0; i < L; ++i) nf += (size_t)(W + 1) * (p[32 + i] ? 2 : 1);
+  if (nbytes != 64 + 4 * nf)
+    return fail(SAND_ERR_FORMAT, "model blob: %zu bytes, expected %zu for L=%u W=%u", nbytes,
+                64 + 4 * nf, L, W);
+  store.resize(nf + 2);
+  std::memcpy(store.data(), p + 64, 4 * nf);   // little-endian host
+  std::memcpy(&store[nf], p + 24, 8);          // the two omegas
+  for (size_t i = 0; i < nf + 2; ++i)
+    if (!std::isfinite(store[i])) return fail(SAND_ERR_FORMAT, "model blob: non-finite value");
+  B.L = (int)L;
+  B.W = (int)W;
+  B.om[0] = store[nf];
+  B.om[1] = store[nf + 1];
+  const float* q = store.data();
+  B.Wm.push_back(q); q += (size_t)W * 3;
+  B.b.push_back(q); q += W;
+  for (uint32_t j = 1; j < L; ++j) {
+    B.Wm.push_back(q); q += (size_t)W * W;
+    B.b.push_back(q); q += W;
+  }
+  for (uint32_t i = 0; i < L; ++i) {
+    B.kind[i] = p[32 + i];
+    if (B.kind[i] == 0) {
+      B.a0.push_back(q); q += W;
+      B.c0.push_back(*q++);
+      B.a1.push_back(nullptr);
+      B.c1.push_back(1.0f);
+    } else {
+      B.a0.push_back(q); q += W;
+      B.c0.push_back(*q++);
+      B.a1.push_back(q); q += W;
+      B.c1.push_back(*q++);
+    }
+  }
+  return SAND_OK;
+}
+
+uint16_t to_bf16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t lsb = (x >> 16) & 1u;
+  return (uint16_t)((x + 0x7fffu + lsb) >> 16);   // round to nearest even (finite inputs)
+}
+
+uint16_t to_f16(float f) {
+  uint32_t x;
+  std::memcpy(&x, &f, 4);
+  const uint32_t sign = (x >> 16) & 0x8000u;
+  const int32_t e = (int32_t)((x >> 23) & 0xff) - 127 + 15;
+  uint32_t m = x & 0x7fffffu;
+  if (e >= 31) return (uint16_t)(sign | 0x7c00u);
+  if (e <= 0) {
+    if (e < -10) return (uint16_t)sign;
+    m |= 0x800000u;
+    const int shift = 14 - e;
+    uint32_t h = m >> shift;
+    const uint32_t rem = m & ((1u << shift) - 1), half = 1u << (shift - 1);
+    if (rem > half || (rem == half && (h & 1))) ++h;
+    return (uint16_t)(sign | h);
+  }
+  uint32_t h = sign | ((uint32_t)e << 10) | (m >> 13);
+  const uint32_t rem = m & 0x1fffu;
+  if (rem > 0x1000u || (rem == 0x1000u && (h & 1))) ++h;
+  return (uint16_t)h;
+}
+
+float from_16(uint16_t v, int prec) {
+  if (prec == PREC_BF16) {
+    const uint32_t x = (uint32_t)v << 16;
+    float f;
+    std::memcpy(&f, &x, 4);
+    return f;
+  }
+  const uint32_t sign = (uint32_t)(v & 0x8000u) << 16;
+  const int e = (v >> 10) & 0x1f;
+  const uint32_t m = v & 0x3ffu;
+  float f;
+  if (e == 0) {
+    f = std::ldexp((float)m, -24);
+  } else {
+    const uint32_t x = ((uint32_t)(e - 15 + 127) << 23) | (m << 13);
+    std::memcpy(&f, &x, 4);
+  }
+  return sign ? -f : f;
+}
+
+// Host-side geometry of the packed layout (mirrors the kernel's Tr/Cfg).
+struct Geo {
+  int BM, L1S, VB, KPS;
+  int RB, KS, CH, L1C;
+  Geo(int prec, int WP) {
+    if (prec == PREC_FP32) {
+      BM = 16; L1S = 1; VB = 4; KPS = 4;
+    } else {
+      BM = 32; L1S = 2; VB = 16; KPS = 16;
+    }
+    RB = WP / BM;
+    KS = WP / KPS;
+    CH = (KS + 1) * 64 * VB + BM * 8;
+    L1C = L1S * 256 + BM * 8;
+  }
+};
+
+// Pack one precision's chunks (layout in sand_internal.h).
+std::vector<char> pack(const Blob& B, int prec, int WP) {
+  const Geo G(prec, WP);
+  const int W = B.W;
+  const size_t total = (size_t)G.RB * G.L1C + (size_t)(B.L - 1) * G.RB * G.CH;
+  std::vector<char> buf(total, 0);
+  const double s1 = (double)B.om[0] / kTwoPi, sh = (double)B.om[1] / kTwoPi;
+  auto tails = [&](float* dst, int layer, int rb) {
+    for (int i = 0; i < G.BM; ++i) {
+      const int u = G.BM * rb + i;
+      dst[i] = u < W ? B.a0[layer][u] : 0.0f;
+      dst[G.BM + i] = (u < W && B.a1[layer]) ? B.a1[layer][u] : 0.0f;
+    }
+  };
+  // layer 1
+  for (int rb = 0; rb < G.RB; ++rb) {
+    char* ch = buf.data() + (size_t)rb * G.L1C;
+    float* A = (float*)ch;
+    for (int st = 0; st < G.L1S; ++st)
+      for (int l = 0; l < 64; ++l) {
+        int m, k;
+        if (prec == PREC_FP32) {
+          m = l & 15;
+          k = l >> 4;
+        } else {
+          m = l & 31;
+          k = 2 * st + (l >> 5);
+        }
+        const int u = G.BM * rb + m;
+        double v = 0.0;
+        if (u < W) v = s1 * (k < 3 ? (double)B.Wm[0][u * 3 + k] : (double)B.b[0][u]);
+        A[st * 64 + l] = (float)v;
+      }
+    tails((float*)(ch + G.L1S * 256), 0, rb);
+  }
+  // hidden layers
+  for (int j = 1; j < B.L; ++j) {
+    const float* Wj = B.Wm[j];
+    const float* bj = B.b[j];
+    for (int rb = 0; rb < G.RB; ++rb) {
+      char* ch = buf.data() + (size_t)G.RB * G.L1C + ((size_t)(j - 1) * G.RB + rb) * G.CH;
+      for (int s = 0; s <= G.KS; ++s)
+        for (int l = 0; l < 64; ++l) {
+          if (prec == PREC_FP32) {
+            const int m = l & 15, g = l >> 4, uo = 16 * rb + m;
+            double v = 0.0;
+            if (s < G.KS) {
+              const int ui = 16 * (s >> 2) + 4 * g + (s & 3);
+              if (uo < W && ui < W) v = sh * (double)Wj[(size_t)uo * W + ui];
+            } else if (g == 0 && uo < W) {
+              v = sh * (double)bj[uo];
+            }
+            ((float*)ch)[s * 64 + l] = (float)v;
+          } else {
+            const int m = l & 31, h = l >> 5, uo = 32 * rb + m;
+            uint16_t* A = (uint16_t*)(ch + ((size_t)s * 64 + l) * 16);
+            auto r16 = [&](double v) { return prec == PREC_BF16 ? to_bf16((float)v) : to_f16((float)v); };
+            for (int p = 0; p < 8; ++p) {
+              double v = 0.0;
+              if (s < G.KS) {
+                const int ui = 16 * s + 8 * (p >> 2) + 4 * h + (p & 3);
+                if (uo < W && ui < W) v = sh * (double)Wj[(size_t)uo * W + ui];
+                A[p] = r16(v);
+              } else {
+                A[p] = 0;
+              }
+            }
+            if (s == G.KS && h == 0 && uo < W) {
+              const double bv = sh * (double)bj[uo];
+              const uint16_t hi = r16(bv);
+              A[0] = hi;
+              A[1] = r16(bv - (double)from_16(hi, prec));
+            }
+          }
+        }
+      tails((float*)(ch + (size_t)(G.KS + 1) * 64 * G.VB), j, rb);
+    }
+  }
+  return buf;
+}
+
+}  // namespace
+
+extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int device,
+                                       sand_model* out) {
+  if (!blob || !out) return fail(SAND_ERR_INVALID, "sand_load_model: null blob or out");
+  *out = nullptr;
+  Blob B;
+  std::vector<float> store;
+  sand_status st = parse_blob(blob, nbytes, B, store);
+  if (st != SAND_OK) return st;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(SAND_ERR_INVALID, "sand_load_model: device %d not available (%d devices)", device,
+                ndev);
+  const int WP = padded_width(B.W);
+  std::vector<char> packs[3];
+  size_t offs[3], total = 0;
+  for (int p = 0; p < 3; ++p) {
+    packs[p] = pack(B, p, WP);
+    offs[p] = total;
+    total += (packs[p].size() + 255) & ~(size_t)255;
+  }
+  DeviceGuard guard(device);
+  if (!guard.ok) return fail(SAND_ERR_DEVICE, "sand_load_model: cannot select device %d", device);
+  int num_cu = 0;
+  hipError_t e = hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return device_fail(e, "sand_load_model: device query");
+  char* dev = nullptr;
+  e = hipMalloc((void**)&dev, total);
+  if (e != hipSuccess) return fail(SAND_ERR_NOMEM, "sand_load_model: %zu device bytes", total);
+  for (int p = 0; p < 3; ++p) {
+    e = hipMemcpy(dev + offs[p], packs[p].data(), packs[p].size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dev);
+      return device_fail(e, "sand_load_model: upload");
+    }
+  }
+  sand_model m = new sand_model_s();
+  m->device = device;
+  m->L = B.L;
+  m->W = B.W;
+  m->WP = WP;
+  m->num_cu = num_cu;
+  m->dev = dev;
+  m->bytes = total;
+  for (int p = 0; p < 3; ++p) {
+    ModelArgs& a = m->args[p];
+    std::memset(&a, 0, sizeof(a));
+    a.chunks = dev + offs[p];
+    a.L = B.L;
+    a.WP = WP;
+    a.chunk_bytes = Geo(p, WP).CH;
+    for (int i = 0; i < B.L; ++i) {
+      a.c0[i] = B.c0[i];
+      a.c1[i] = B.c1[i];
+    }
+  }
+  *out = m;
+  return SAND_OK;
+}
+
+extern "C" void sand_free_model(sand_model m) {
+  if (!m) return;
+  DeviceGuard guard(m->device);
+  (void)hipFree(m->dev);
+  delete m;
+}
+
+extern "C" sand_status sand_model_info(sand_model m, int32_t* L, int32_t* W) {
+  if (!m) return fail(SAND_ERR_INVALID, "sand_model_info: null model");
+  if (L) *L = m->L;
+  if (W) *W = m->W;
+  return SAND_OK;
+}
+
+// ------------------------------------------------------------ depth maps --
+
+extern "C" sand_status sand_build_depthmap(sand_model m, const uint8_t* depth_host, int32_t R,
+                                           const float* far_host, sand_depthmap* out) {
+  if (!m || !depth_host || !out)
+    return fail(SAND_ERR_INVALID, "sand_build_depthmap: null model, map or out");
+  *out = nullptr;
+  if (R < 2 || R > 1024 || (R & (R - 1)) != 0)
+    return fail(SAND_ERR_INVALID, "sand_build_depthmap: R=%d is not a power of two in 2..1024", R);
+  const size_t cells = (size_t)R * R * R;
+  bool has_zero = false;
+  for (size_t i = 0; i < cells; ++i) {
+    if (depth_host[i] > m->L)
+      return fail(SAND_ERR_FORMAT, "sand_build_depthmap: depth %u at cell %zu exceeds L=%d",
+                  depth_host[i], i, m->L);
+    has_zero |= depth_host[i] == 0;
+  }
+  if (has_zero && !far_host)
+    return fail(SAND_ERR_FORMAT, "sand_build_depthmap: depth-0 cells need far-field values");
+  DeviceGuard guard(m->device);
+  if (!guard.ok) return fail(SAND_ERR_DEVICE, "sand_build_depthmap: cannot select device");
+  uint8_t* d = nullptr;
+  float* f = nullptr;
+  hipError_t e = hipMalloc((void**)&d, cells);
+  if (e != hipSuccess) return fail(SAND_ERR_NOMEM, "sand_build_depthmap: %zu bytes", cells);
+  e = hipMemcpy(d, depth_host, cells, hipMemcpyHostToDevice);
+  if (e == hipSuccess && far_host) {
+    e = hipMalloc((void**)&f, cells * 4);
+    if (e == hipSuccess) e = hipMemcpy(f, far_host, cells * 4, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    if (f) (void)hipFree(f);
+    return device_fail(e, "sand_build_depthmap: upload");
+  }
+  sand_depthmap dm = new sand_depthmap_s();
+  dm->model = m;
+  dm->R = R;
+  dm->depth = d;
+  dm->far = f;
+  *out = dm;
+  return SAND_OK;
+}
+
+extern "C" void sand_free_depthmap(sand_depthmap dm) {
+  if (!dm) return;
+  DeviceGuard guard(dm->model->device);
+  (void)hipFree(dm->depth);
+  if (dm->far) (void)hipFree(dm->far);
+  delete dm;
+}
+
+// --------------------------------------------------------------- queries --
+
+namespace sand {
+
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+WorkspaceLayout workspace_layout(int64_t n) {
+  WorkspaceLayout w{};
+  if (n <= 0) return w;
+  const size_t nblk = (size_t)((n + kLookupChunk - 1) / kLookupChunk);
+  w.depth = 0;
+  w.perm = al((size_t)n);
+  w.counts = w.perm + al(4 * (size_t)n);
+  w.plan = w.counts + al(nblk * kBuckets * 4);
+  w.total = w.plan + al(sizeof(Plan));
+  w.nblk = (int64_t)nblk;
+  return w;
+}
+
+sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const float* xyz,
+                        int64_t n, const void* out, const sand_query_opts& o) {
+  if (!m) return fail(SAND_ERR_INVALID, "%s: null model", who);
+  if (n < 0 || n > 2147483647LL) return fail(SAND_ERR_INVALID, "%s: n=%lld out of range", who,
+                                             (long long)n);
+  if (n > 0 && (!xyz || !out)) return fail(SAND_ERR_INVALID, "%s: null point or output buffer", who);
+  if (((uintptr_t)xyz & 3u) != 0) return fail(SAND_ERR_INVALID, "%s: points not 4-byte aligned", who);
+  if (o.precision < 0 || o.precision > 2)
+    return fail(SAND_ERR_INVALID, "%s: precision %d", who, o.precision);
+  if (o.mode < 0 || o.mode > 2) return fail(SAND_ERR_INVALID, "%s: mode %d", who, o.mode);
+  if (o.max_depth < 0) return fail(SAND_ERR_INVALID, "%s: max_depth %d", who, o.max_depth);
+  if (o.reserved != 0) return fail(SAND_ERR_INVALID, "%s: reserved field not zero", who);
+  if (dm && dm->model != m) return fail(SAND_ERR_INVALID, "%s: map belongs to another model", who);
+  if (o.mode == SAND_ADAPTIVE && !dm) return fail(SAND_ERR_INVALID, "%s: adaptive mode needs a map", who);
+  if (o.mode == SAND_FORCED && n > 0 && !o.forced_depth)
+    return fail(SAND_ERR_INVALID, "%s: forced mode needs forced_depth", who);
+  if (o.workspace && o.workspace_bytes < workspace_layout(n).total)
+    return fail(SAND_ERR_INVALID, "%s: workspace of %zu bytes, need %zu", who, o.workspace_bytes,
+                workspace_layout(n).total);
+  return SAND_OK;
+}
+
+// Lookup + bucketing + T-MLP for n points. `ws` must hold workspace_layout(n).
+sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
+                        const sand_query_opts& o, char* ws, hipStream_t s) {
+  const int prec = o.precision;
+  QueryArgs qa{};
+  qa.m = m->args[prec];
+  qa.xyz = xyz;
+  qa.sdf = sdf;
+  qa.n = n;
+  hipError_t e;
+  if (o.mode == SAND_FULL) {
+    const int d = (o.max_depth > 0 && o.max_depth < m->L) ? o.max_depth : m->L;
+    qa.full_depth = d;
+    if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
+    if (o.depth_out && (e = launch_fill_u8(o.depth_out, n, (uint8_t)d, s)) != hipSuccess)
+      return device_fail(e, "depth fill launch");
+    return SAND_OK;
+  }
+  const WorkspaceLayout w = workspace_layout(n);
+  uint8_t* depth = o.depth_out ? o.depth_out : (uint8_t*)(ws + w.depth);
+  int32_t* perm = (int32_t*)(ws + w.perm);
+  int32_t* counts = (int32_t*)(ws + w.counts);
+  Plan* plan = (Plan*)(ws + w.plan);
+  const uint8_t* map = dm ? dm->depth : nullptr;
+  const float* far = dm ? dm->far : nullptr;
+  const int R = dm ? dm->R : 2;
+  if ((e = launch_lookup_count(xyz, n, map, R, far, o.forced_depth, o.mode, m->L, o.max_depth, depth,
+                               sdf, counts, s)) != hipSuccess)
+    return device_fail(e, "lookup launch");
+  if ((e = launch_scan(counts, w.nblk, m->L, tmlp_tile_points(prec), plan, s)) != hipSuccess)
+    return device_fail(e, "scan launch");
+  if ((e = launch_scatter(depth, n, counts, perm, s)) != hipSuccess)
+    return device_fail(e, "scatter launch");
+  qa.perm = perm;
+  qa.plan = plan;
+  if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
+  return SAND_OK;
+}
+
+}  // namespace sand
+
+extern "C" size_t sand_query_workspace_size(int64_t n) { return workspace_layout(n).total; }
+
+extern "C" sand_status sand_query(sand_model m, sand_depthmap dm, const float* xyz, int64_t n,
+                                  float* sdf, const sand_query_opts* opts, void* stream) {
+  sand_query_opts o;
+  if (opts) o = *opts; else sand_query_opts_init(&o);
+  sand_status st = check_query("sand_query", m, dm, xyz, n, sdf, o);
+  if (st != SAND_OK || n == 0) return st;
+  DeviceGuard guard(m->device);
+  if (!guard.ok) return fail(SAND_ERR_DEVICE, "sand_query: cannot select device");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)o.workspace;
+  bool owned = false;
+  if (o.mode != SAND_FULL && !ws) {
+    hipError_t e = hipMallocAsync((void**)&ws, workspace_layout(n).total, s);
+    if (e != hipSuccess) return fail(SAND_ERR_NOMEM, "sand_query: scratch of %zu bytes",
+                                     workspace_layout(n).total);
+    owned = true;
+  }
+  st = run_forward(m, dm, xyz, n, sdf, o, ws, s);
+  if (owned) (void)hipFreeAsync(ws, s);
+  return st;
+}
+
+extern "C" sand_status sand_query_grad(sand_model m, sand_depthmap dm, const float* xyz, int64_t n,
+                                       const float* dy, float* sdf, float* grad,
+                                       const sand_query_opts* opts, void* stream) {
+  (void)m; (void)dm; (void)xyz; (void)n; (void)dy; (void)sdf; (void)grad; (void)opts; (void)stream;
+  return fail(SAND_ERR_UNSUPPORTED, "sand_query_grad: not built yet");
+}

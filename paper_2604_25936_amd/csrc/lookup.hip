@@ -1,0 +1,251 @@
+// Depth lookup and stable bucketing of query points by exit depth.
+//
+// Inference first reads every point's exit depth from the network-depth map
+// and answers far-field points (depth 0) from the stored value (Sec. 3.4,
+// Eq. 7); the remaining points are evaluated to their own depth. To run
+// points of equal depth together, three launches build a permutation that
+// groups point indices by depth, stable within each group:
+//   1. k_lookup_count: per 4096-point chunk, depth per point (written as
+//      uint8), far values written straight to the output, and a per-chunk
+//      histogram built from wavefront ballots;
+//   2. k_scan: one workgroup turns the per-chunk histograms into per-chunk
+//      output offsets and writes the tile plan (deepest bucket first);
+//   3. k_scatter: per chunk again, each point's rank among equal depths
+//      (ballot + popcount below the lane) gives its slot in the permutation.
+// Point coordinates are read through LDS so that every global load of a
+// wavefront covers 256 contiguous bytes.
+
+#include "sand_internal.h"
+
+namespace sand {
+
+namespace {
+
+constexpr int kRounds = kLookupChunk / kLookupThreads;
+
+__device__ __forceinline__ int cell_index(float x, float s, int half) {
+  // x * s is exact (s a power of two); clamp before the float->int step so
+  // that out-of-cube points and NaN land in a border cell (NaN -> cell 0).
+  float v = x * s;
+  if (!(v >= -s)) v = -s;
+  if (v > s - 1.0f) v = s - 1.0f;
+  return (int)floorf(v) + half;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Add the wavefront's points to hist[depth]: one LDS atomic per distinct
+// depth present in the wavefront.
+__device__ __forceinline__ void wave_histogram(int d, bool valid, int* hist) {
+  uint64_t todo = __ballot(valid);
+  const int lane = threadIdx.x & 63;
+  while (todo) {
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const int v = __shfl(d, leader);
+    const uint64_t m = __ballot(valid && d == v);
+    if (lane == leader) atomicAdd(&hist[v], __popcll(m));
+    todo &= ~m;
+  }
+}
+
+__global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
+    const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
+    int R, const float* __restrict__ far, const uint8_t* __restrict__ forced,
+    int mode, int L, int max_depth, uint8_t* __restrict__ depth,
+    float* __restrict__ sdf, int32_t* __restrict__ counts) {
+  __shared__ float sx[3 * kLookupThreads];
+  __shared__ int hist[kBuckets];
+  const int t = threadIdx.x;
+  if (t < kBuckets) hist[t] = 0;
+  const int64_t base = (int64_t)blockIdx.x * kLookupChunk;
+  const int half = R >> 1;
+  const float s = (float)half;
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t q0 = base + (int64_t)r * kLookupThreads;
+    if (q0 >= n) break;
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+      const int64_t f = q0 * 3 + k * kLookupThreads + t;
+      sx[k * kLookupThreads + t] = f < 3 * n ? xyz[f] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t q = q0 + t;
+    const bool valid = q < n;
+    int d = 0;
+    if (valid) {
+      const float x = sx[3 * t], y = sx[3 * t + 1], z = sx[3 * t + 2];
+      int cell = -1;
+      if (map != nullptr) {
+        const int ix = cell_index(x, s, half), iy = cell_index(y, s, half),
+                  iz = cell_index(z, s, half);
+        cell = (ix * R + iy) * R + iz;
+      }
+      if (mode == 1) {
+        d = L;
+      } else if (mode == 2) {
+        d = forced[q];
+        if (d > L) d = L;
+      } else {
+        d = map[cell];
+      }
+      if (max_depth > 0 && d > max_depth) d = max_depth;
+      depth[q] = (uint8_t)d;
+      if (d == 0) sdf[q] = (far != nullptr && cell >= 0) ? far[cell] : __builtin_nanf("");
+    }
+    wave_histogram(d, valid, hist);
+  }
+  __syncthreads();
+  if (t < kBuckets) counts[(int64_t)blockIdx.x * kBuckets + t] = hist[t];
+}
+
+constexpr int kScanThreads = 256;
+
+// One workgroup: per-chunk histograms -> per-chunk bucket offsets (in
+// place) and the tile plan. Bucket d >= 1 occupies perm slots
+// [start[d], start[d] + count[d]); depth-0 points are not in the permutation.
+__global__ __launch_bounds__(kScanThreads) void k_scan(int32_t* __restrict__ counts,
+                                                      int64_t nblk, int L, int tile_q,
+                                                      Plan* __restrict__ plan) {
+  __shared__ int64_t part[kScanThreads][kBuckets];
+  __shared__ int64_t start[kBuckets];
+  const int t = threadIdx.x;
+  const int64_t per = (nblk + kScanThreads - 1) / kScanThreads;
+  const int64_t b0 = t * per;
+  const int64_t b1 = b0 + per < nblk ? b0 + per : nblk;
+  int64_t sum[kBuckets];
+  for (int d = 0; d < kBuckets; ++d) sum[d] = 0;
+  for (int64_t b = b0; b < b1; ++b)
+    for (int d = 0; d < kBuckets; ++d) sum[d] += counts[b * kBuckets + d];
+  for (int d = 0; d < kBuckets; ++d) part[t][d] = sum[d];
+  __syncthreads();
+  if (t < kBuckets) {
+    // exclusive scan over threads for bucket t
+    int64_t run = 0;
+    for (int k = 0; k < kScanThreads; ++k) {
+      const int64_t v = part[k][t];
+      part[k][t] = run;
+      run += v;
+    }
+    plan->count[t] = run;
+    start[t] = run;  // temporarily the total
+  }
+  __syncthreads();
+  if (t == 0) {
+    int64_t run = 0;
+    for (int d = 1; d < kBuckets; ++d) {
+      const int64_t tot = start[d];
+      start[d] = run;
+      run += tot;
+    }
+    start[0] = -1;
+    int64_t tiles = 0;
+    plan->tile_end[kBuckets] = 0;
+    for (int d = kBuckets - 1; d >= 1; --d) {
+      const int64_t cnt = d <= L ? plan->count[d] : 0;
+      tiles += (cnt + tile_q - 1) / tile_q;
+      plan->tile_end[d] = tiles;
+    }
+    plan->tile_end[0] = tiles;
+    plan->total_tiles = tiles;
+    plan->tile_q = tile_q;
+    for (int d = 0; d < kBuckets; ++d) plan->start[d] = start[d];
+  }
+  __syncthreads();
+  int64_t run[kBuckets];
+  for (int d = 0; d < kBuckets; ++d) run[d] = start[d] + part[t][d];
+  for (int64_t b = b0; b < b1; ++b)
+    for (int d = 0; d < kBuckets; ++d) {
+      const int32_t c = counts[b * kBuckets + d];
+      counts[b * kBuckets + d] = (int32_t)run[d];
+      run[d] += c;
+    }
+}
+
+__global__ __launch_bounds__(kLookupThreads) void k_scatter(
+    const uint8_t* __restrict__ depth, int64_t n, const int32_t* __restrict__ offs,
+    int32_t* __restrict__ perm) {
+  __shared__ int run[kBuckets];
+  __shared__ int wcnt[kLookupThreads / 64][kBuckets];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kLookupChunk;
+  if (t < kBuckets) run[t] = offs[(int64_t)blockIdx.x * kBuckets + t];
+  for (int r = 0; r < kRounds; ++r) {
+    const int64_t q0 = base + (int64_t)r * kLookupThreads;
+    if (q0 >= n) break;
+    __syncthreads();  // the previous round's update of run[] has read wcnt
+    if (t < kBuckets * (kLookupThreads / 64)) wcnt[t / kBuckets][t % kBuckets] = 0;
+    __syncthreads();
+    const int64_t q = q0 + t;
+    const int d = q < n ? depth[q] : 0;
+    const bool valid = q < n && d > 0;
+    // rank among equal depths within the wavefront
+    uint64_t todo = __ballot(valid);
+    int rank = 0;
+    while (todo) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const int v = __shfl(d, leader);
+      const uint64_t m = __ballot(valid && d == v);
+      if (valid && d == v) rank = __popcll(m & lanemask_lt());
+      if (lane == leader) wcnt[w][v] = __popcll(m);
+      todo &= ~m;
+    }
+    __syncthreads();
+    if (valid) {
+      int pos = run[d] + rank;
+      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+      perm[pos] = (int32_t)q;
+    }
+    __syncthreads();
+    if (t < kBuckets) {
+      int add = 0;
+      for (int k = 0; k < kLookupThreads / 64; ++k) add += wcnt[k][t];
+      run[t] += add;
+    }
+  }
+}
+
+__global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map, int R,
+                               const float* far, const uint8_t* forced, int mode, int L,
+                               int max_depth, uint8_t* depth, float* sdf, int32_t* counts,
+                               hipStream_t s) {
+  const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
+  hipLaunchKernelGGL(k_lookup_count, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, xyz,
+                     n, map, R, far, forced, mode, L, max_depth, depth, sdf, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q, Plan* plan,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, nblk, L, tile_q,
+                     plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
+                          int32_t* perm, hipStream_t s) {
+  const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, depth, n,
+                     offs, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace sand

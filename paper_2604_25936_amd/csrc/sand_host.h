@@ -1,0 +1,50 @@
+// Host-side internals shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/sand.h"
+#include "sand_internal.h"
+
+struct sand_model_s {
+  int device = 0;
+  int L = 0, W = 0, WP = 0;
+  int num_cu = 0;
+  char* dev = nullptr;        // one allocation holding the three packed precisions
+  size_t bytes = 0;
+  sand::ModelArgs args[3];    // indexed by sand_precision
+};
+
+struct sand_depthmap_s {
+  sand_model model = nullptr;
+  int R = 0;
+  uint8_t* depth = nullptr;   // device [R^3]
+  float* far = nullptr;       // device [R^3] or null
+};
+
+namespace sand {
+
+sand_status fail(sand_status st, const char* fmt, ...);
+sand_status device_fail(hipError_t e, const char* what);
+
+// Selects a device for the current thread and restores the previous one.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+};
+
+// Byte offsets of the per-query scratch regions.
+struct WorkspaceLayout {
+  size_t depth, perm, counts, plan, total;
+  int64_t nblk;
+};
+WorkspaceLayout workspace_layout(int64_t n);
+
+sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const float* xyz,
+                        int64_t n, const void* out, const sand_query_opts& o);
+sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
+                        const sand_query_opts& o, char* ws, hipStream_t s);
+
+}  // namespace sand

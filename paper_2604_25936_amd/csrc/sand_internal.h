@@ -1,0 +1,98 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+//
+// Packed model layout on the device (built once by sand_load_model):
+//
+//   The hidden width W is padded to WP (64, 128, 256 or 352) with zero rows
+//   and columns, and the output units of every layer are cut into blocks of
+//   BM units (BM = 16 for FP32, 32 for BF16/FP16). Each (layer, block) pair
+//   is one "chunk": the MFMA A-operand tiles of that block in exactly the
+//   per-lane order the kernel reads them, followed by the block's FP32 tail
+//   weights a0[BM], a1[BM]:
+//
+//     layer 1, FP32 path (16x16x4 FP32 MFMA, K = 4 = x, y, z, bias):
+//        float A[1 step][64 lanes], then tails             256 + 128 B
+//     layer 1, BF16/FP16 path (32x32x2 FP32 MFMA, 2 K steps):
+//        float A[2 steps][64 lanes], then tails            512 + 256 B
+//     layer j >= 2, FP32 (16x16x4 MFMA, WP/4 K steps + 1 bias step):
+//        float A[WP/4 + 1][64 lanes], then tails
+//     layer j >= 2, BF16/FP16 (32x32x16 MFMA, WP/16 K steps + 1 bias step):
+//        u16   A[WP/16 + 1][64 lanes][8], then tails
+//
+//   Weights and biases are pre-multiplied by omega_j / (2 pi) so that one
+//   hardware sine in revolutions gives sin(omega_j (W h + b)). The K order of
+//   layer j's weights is permuted so that the accumulator registers of
+//   layer j-1 are, as they stand, the B operand of layer j (activations
+//   never leave registers). A linear tail is stored as a0 = a, a1 = 0 with
+//   c0 = c, c1 = 1, so every tail is evaluated as (a0.h + c0)(a1.h + c1).
+#pragma once
+
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace sand {
+
+constexpr int kMaxLayers = 16;
+constexpr int kMaxWidth = 352;
+constexpr int kBuckets = kMaxLayers + 1;   // exit depths 0..16
+constexpr int kLookupThreads = 256;
+constexpr int kLookupChunk = 4096;         // points per lookup block
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
+
+// Padded widths the kernels are built for.
+inline int padded_width(int W) {
+  if (W <= 64) return 64;
+  if (W <= 128) return 128;
+  if (W <= 256) return 256;
+  return 352;
+}
+
+
+// Device-side description of a packed model for one precision.
+struct ModelArgs {
+  const char* chunks;      // layer-1 chunks, then hidden chunks (layer-major)
+  int L;                   // hidden layers
+  int WP;                  // padded width
+  size_t chunk_bytes;      // bytes of one hidden chunk
+  float c0[kMaxLayers];    // tail bias of the first factor
+  float c1[kMaxLayers];    // tail bias of the second factor (1 for linear)
+};
+
+// Bucketed work plan written on the device by the scan kernel.
+struct Plan {
+  int64_t start[kBuckets];      // first perm slot of depth bucket d
+  int64_t count[kBuckets];      // points in bucket d
+  int64_t tile_end[kBuckets + 1];  // tiles of depths >= d (tile_end[L+1] = 0):
+                                   // depth d owns [tile_end[d+1], tile_end[d])
+  int64_t total_tiles;
+  int32_t tile_q;               // points per tile the plan was cut for
+  int32_t pad;
+};
+
+// Everything one forward launch needs.
+struct QueryArgs {
+  ModelArgs m;
+  const float* xyz;        // [n][3]
+  float* sdf;              // [n]
+  const int32_t* perm;     // bucketed point order, or null (FULL mode)
+  const Plan* plan;        // device plan, or null (FULL mode)
+  int64_t n;
+  int full_depth;          // FULL mode: the depth every point runs to
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map,
+                               int R, const float* far, const uint8_t* forced,
+                               int mode, int L, int max_depth, uint8_t* depth,
+                               float* sdf, int32_t* counts, hipStream_t s);
+hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q,
+                       Plan* plan, hipStream_t s);
+hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
+                          int32_t* perm, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+
+int tmlp_tile_points(int prec);
+hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s);
+
+}  // namespace sand

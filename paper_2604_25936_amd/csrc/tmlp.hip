@@ -1,0 +1,375 @@
+// Fused T-MLP evaluation on the matrix cores (gfx950).
+//
+// One workgroup evaluates a tile of points that share an exit depth d
+// (Sec. 3.4): hidden layers 1..d, each layer's tail, and the accumulated
+// output y_d = t_1 + ... + t_d (Eq. 2), with tails of the product form of
+// Eq. 3 where the model has them. Each result goes straight to its point's
+// slot in the output.
+//
+// Data flow of one wavefront (one block of NQ points):
+//  * Points are the N dimension of every product: Z_j = W_j H_{j-1}, with
+//    W_j the A operand (from LDS) and H_{j-1} the B operand (registers).
+//    BF16/FP16 use 32x32x16 MFMAs (32 points per wavefront, output blocks
+//    of 32 units); FP32 uses 16x16x4 MFMAs (16 points, blocks of 16 units).
+//    The packed weights' K order is permuted so that a layer's FP32
+//    accumulators, after sine and conversion, are the next layer's B
+//    operand as they stand: activations never leave registers.
+//  * Layer 1 (K = 3 plus bias) is an FP32 MFMA with B = (x, y, z, 1): its
+//    omega-scaled argument is FP32 in every precision.
+//  * Hidden-layer bias: one extra K step against a constant B = 1 (two
+//    16-bit columns, high and low part, for BF16/FP16).
+//  * Epilogue per element: hardware sine in revolutions (weights carry
+//    omega/(2 pi)), two FP32 FMAs for the two tail factors, pack. The lanes
+//    holding disjoint units of one point are summed by cross-lane exchange.
+//  * Weights stream through a two-slot LDS ring, one output block
+//    ("chunk") at a time: direct global-to-LDS loads of chunk c+1 are in
+//    flight while chunk c feeds the MFMAs.
+//  * Eight wavefronts per workgroup, two per SIMD: while one wavefront runs
+//    its sine/tail epilogue on the vector ALU the other keeps the matrix
+//    core busy.
+// The grid is persistent (one workgroup per CU) and strides over tiles,
+// which the plan orders deepest bucket first.
+
+#include "sand_internal.h"
+
+namespace sand {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Per-precision MFMA geometry. For lane l: `col` is its point within the
+// wavefront's block, `grp` its row group; accumulator register e holds one
+// unit of the current output block (see tail_row and put).
+template <int PREC>
+struct Tr;
+
+template <>
+struct Tr<PREC_FP32> {
+  using V = float;
+  using Acc = f32x4;
+  static constexpr int BM = 16;   // units per output block
+  static constexpr int NQ = 16;   // points per wavefront
+  static constexpr int NR = 4;    // accumulator registers per lane
+  static constexpr int SPB = 4;   // K steps per block of input units
+  static constexpr int VB = 4;    // A-operand bytes per lane per K step
+  static constexpr int L1S = 1;   // layer-1 MFMA steps
+  __device__ __forceinline__ static int col(int lane) { return lane & 15; }
+  __device__ __forceinline__ static int grp(int lane) { return lane >> 4; }
+  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) { return mma(a, b, c); }
+  __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
+    return g == 0 ? x : g == 1 ? y : g == 2 ? z : 1.0f;
+  }
+  __device__ __forceinline__ static V bias_b(int g) { return g == 0 ? 1.0f : 0.0f; }
+  // offset (in floats) of the 4 tail rows that registers 4i..4i+3 hold
+  __device__ __forceinline__ static int tail_row(int i, int g) { return 4 * g; }
+  template <int KS>
+  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
+    act[4 * rb + e] = v;
+  }
+  __device__ __forceinline__ static float lane_sum(float v) {
+    v += __shfl_xor(v, 16);
+    return v + __shfl_xor(v, 32);
+  }
+};
+
+template <int PREC>
+struct Tr16 {
+  using Acc = f32x16;
+  static constexpr int BM = 32;
+  static constexpr int NQ = 32;
+  static constexpr int NR = 16;
+  static constexpr int SPB = 2;
+  static constexpr int VB = 16;
+  static constexpr int L1S = 2;
+  __device__ __forceinline__ static int col(int lane) { return lane & 31; }
+  __device__ __forceinline__ static int grp(int lane) { return lane >> 5; }
+  __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
+    return step == 0 ? (g == 0 ? x : y) : (g == 0 ? z : 1.0f);
+  }
+  __device__ __forceinline__ static int tail_row(int i, int g) { return 8 * i + 4 * g; }
+  __device__ __forceinline__ static float lane_sum(float v) { return v + __shfl_xor(v, 32); }
+};
+
+template <>
+struct Tr<PREC_BF16> : Tr16<PREC_BF16> {
+  using V = bf16x8;
+  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static V bias_b(int g) {
+    const __bf16 one = (__bf16)(g == 0 ? 1.0f : 0.0f), z = (__bf16)0.0f;
+    return V{one, one, z, z, z, z, z, z};
+  }
+  template <int KS>
+  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
+    act[2 * rb + (e >> 3)][e & 7] = (__bf16)v;
+  }
+};
+
+template <>
+struct Tr<PREC_FP16> : Tr16<PREC_FP16> {
+  using V = f16x8;
+  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static V bias_b(int g) {
+    const _Float16 one = (_Float16)(g == 0 ? 1.0f : 0.0f), z = (_Float16)0.0f;
+    return V{one, one, z, z, z, z, z, z};
+  }
+  template <int KS>
+  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
+    act[2 * rb + (e >> 3)][e & 7] = (_Float16)v;
+  }
+};
+
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+
+template <int PREC, int WP>
+struct Cfg {
+  using T = Tr<PREC>;
+  static constexpr int NW = 8;
+  static constexpr int NT = NW * 64;
+  static constexpr int Q = NW * T::NQ;          // points per tile
+  static constexpr int RB = WP / T::BM;         // output blocks per layer
+  static constexpr int KS = RB * T::SPB;        // K steps of a hidden product
+  static constexpr int TAIL_OFF = (KS + 1) * 64 * T::VB;
+  static constexpr int CH = TAIL_OFF + T::BM * 8;
+  static constexpr int NP = CH / 16;                 // 16-byte pieces per chunk
+  static constexpr int WL = (NP + 64 * NW - 1) / (64 * NW);  // loads per wavefront
+  static constexpr int L1C = T::L1S * 256 + T::BM * 8;   // layer-1 chunk bytes
+  static constexpr int L1B = RB * L1C;
+  static constexpr int LDS = 2 * CH + L1B;
+  static_assert(CH % 16 == 0 && L1B % 16 == 0, "chunks are whole 16-byte pieces");
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Start copying one chunk from global memory into an LDS slot without
+// passing through registers: each wavefront-wide load moves 64 pieces of
+// 16 bytes to 1 KB of LDS. Completion is awaited (vmcnt) before the next
+// workgroup barrier.
+template <int PREC, int WP>
+__device__ __forceinline__ void load_chunk(const char* __restrict__ src, char* dst, int wave,
+                                           int lane) {
+  using C = Cfg<PREC, WP>;
+#pragma unroll
+  for (int k = 0; k < C::WL; ++k) {
+    const int q = k * C::NW + wave;
+    const int piece = q * 64 + lane;
+    if (q * 64 < C::NP && piece < C::NP)
+      __builtin_amdgcn_global_load_lds((const void*)(src + piece * 16), (lds_void*)(dst + q * 1024),
+                                       16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void wait_chunk() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Epilogue of one output block: sine, tail partial sums, pack for the next layer.
+template <int PREC, int KS>
+__device__ __forceinline__ void epilogue(const char* tails, int g, int rb,
+                                         const typename Tr<PREC>::Acc& acc,
+                                         typename Tr<PREC>::V (&out)[KS], float& s0, float& s1) {
+  using T = Tr<PREC>;
+#pragma unroll
+  for (int i = 0; i < T::NR / 4; ++i) {
+    const int row = T::tail_row(i, g);
+    const f32x4 ta = *(const f32x4*)(tails + row * 4);
+    const f32x4 tb = *(const f32x4*)(tails + (T::BM + row) * 4);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = 4 * i + k;
+      const float v = sin_rev(acc[e]);
+      s0 = fmaf(ta[k], v, s0);
+      s1 = fmaf(tb[k], v, s1);
+      T::template put<KS>(out, rb, e, v);
+    }
+  }
+}
+
+// An output block's epilogue is pure register arithmetic, so the compiler
+// may sink it past the following barriers and keep every block's
+// accumulators and tail weights live at once (spilling to scratch). An
+// empty asm that reads the block's results pins the epilogue in place.
+template <int PREC, int KS>
+__device__ __forceinline__ void pin_block(const typename Tr<PREC>::V (&out)[KS], int rb, float s0,
+                                          float s1) {
+  using T = Tr<PREC>;
+  asm volatile("" ::"v"(s0), "v"(s1));
+  if constexpr (T::VB == 16) {
+    asm volatile("" ::"v"(out[2 * rb]), "v"(out[2 * rb + 1]));
+  } else {
+#pragma unroll
+    for (int e = 0; e < T::NR; ++e) asm volatile("" ::"v"(out[4 * rb + e]));
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ float tail_value(float s0, float s1, float c0, float c1) {
+  using T = Tr<PREC>;
+  return (T::lane_sum(s0) + c0) * (T::lane_sum(s1) + c1);
+}
+
+// One hidden layer: in -> out, streaming its RB chunks through the LDS ring.
+// c is the tile's running chunk index, nc its chunk count.
+template <int PREC, int WP>
+__device__ __forceinline__ float hidden_layer(const char* __restrict__ hidden, char* ring,
+                                              int wave, int lane, int g, int& c, int nc,
+                                              const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
+                                              typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
+                                              float c0, float c1) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  float s0 = 0.0f, s1 = 0.0f;
+  const V bb = T::bias_b(g);
+#pragma unroll
+  for (int rb = 0; rb < C::RB; ++rb) {
+    const bool pre = c + 1 < nc;
+    if (pre)
+      load_chunk<PREC, WP>(hidden + (size_t)(c + 1) * C::CH, ring + ((c + 1) & 1) * C::CH, wave,
+                           lane);
+    const char* slot = ring + (c & 1) * C::CH;
+    typename T::Acc acc = {};
+#pragma unroll
+    for (int s = 0; s < C::KS; ++s) {
+      const V a = *(const V*)(slot + (s * 64 + lane) * T::VB);
+      acc = T::mma(a, in[s], acc);
+    }
+    acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb, acc);
+    epilogue<PREC, C::KS>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1);
+    pin_block<PREC, C::KS>(out, rb, s0, s1);
+    if (pre) wait_chunk();
+    __syncthreads();
+    ++c;
+  }
+  return tail_value<PREC>(s0, s1, c0, c1);
+}
+
+template <int PREC, int WP>
+__global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  constexpr int Q = C::Q;
+  __shared__ __attribute__((aligned(16))) char lds[C::LDS];
+  char* ring = lds;
+  char* l1 = lds + 2 * C::CH;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = T::grp(lane), col = T::col(lane);
+
+  for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)a.m.chunks)[i];
+  __syncthreads();
+  const char* hidden = a.m.chunks + C::L1B;
+  const int L = a.m.L;
+  const int64_t total = a.plan ? a.plan->total_tiles : (a.n + Q - 1) / Q;
+
+  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    int d;
+    int64_t start, cnt;
+    if (a.plan) {
+      d = 1;
+      for (int dd = L; dd >= 1; --dd)
+        if (tile < a.plan->tile_end[dd]) {
+          d = dd;
+          break;
+        }
+      const int64_t local = tile - a.plan->tile_end[d + 1];
+      start = a.plan->start[d] + local * Q;
+      cnt = a.plan->count[d] - local * Q;
+    } else {
+      d = a.full_depth;
+      start = tile * Q;
+      cnt = a.n - start;
+    }
+    if (cnt > Q) cnt = Q;
+
+    // This wavefront's point; every lane of the same column holds it.
+    const int qi = wave * T::NQ + col;
+    const bool ok = qi < cnt;
+    int64_t gi = 0;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (ok) {
+      gi = a.perm ? (int64_t)a.perm[start + qi] : start + qi;
+      const float* p = a.xyz + 3 * gi;
+      px = p[0];
+      py = p[1];
+      pz = p[2];
+    }
+
+    V actA[C::KS], actB[C::KS];
+    float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb) {
+      const char* ch = l1 + rb * C::L1C;
+      typename T::Acc acc = {};
+#pragma unroll
+      for (int st = 0; st < T::L1S; ++st)
+        acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
+      epilogue<PREC, C::KS>(ch + T::L1S * 256, g, rb, acc, actA, s0, s1);
+      pin_block<PREC, C::KS>(actA, rb, s0, s1);
+    }
+    float y = tail_value<PREC>(s0, s1, a.m.c0[0], a.m.c1[0]);
+
+    const int nc = (d - 1) * C::RB;
+    int c = 0;
+    if (nc > 0) {
+      load_chunk<PREC, WP>(hidden, ring, wave, lane);
+      wait_chunk();
+      __syncthreads();
+    }
+    for (int j = 2; j <= d; j += 2) {
+      y += hidden_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, actA, actB, a.m.c0[j - 1],
+                                  a.m.c1[j - 1]);
+      if (j + 1 > d) break;
+      y += hidden_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, actB, actA, a.m.c0[j],
+                                  a.m.c1[j]);
+    }
+    if (g == 0 && ok) a.sdf[gi] = y;
+  }
+}
+
+template <int PREC, int WP>
+hipError_t launch_one(const QueryArgs& a, int num_cu, hipStream_t s) {
+  using C = Cfg<PREC, WP>;
+  int64_t grid = num_cu;
+  if (!a.plan) {
+    const int64_t tiles = (a.n + C::Q - 1) / C::Q;
+    if (tiles < grid) grid = tiles;
+  }
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((k_tmlp<PREC, WP>), dim3((unsigned)grid), dim3(C::NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_prec(const QueryArgs& a, int num_cu, hipStream_t s) {
+  switch (a.m.WP) {
+    case 64: return launch_one<PREC, 64>(a, num_cu, s);
+    case 128: return launch_one<PREC, 128>(a, num_cu, s);
+    case 256: return launch_one<PREC, 256>(a, num_cu, s);
+    case 352: return launch_one<PREC, 352>(a, num_cu, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int tmlp_tile_points(int prec) { return 8 * (prec == PREC_FP32 ? 16 : 32); }
+
+hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s) {
+  if (prec == PREC_FP32) return launch_prec<PREC_FP32>(a, num_cu, s);
+  if (prec == PREC_BF16) return launch_prec<PREC_BF16>(a, num_cu, s);
+  return launch_prec<PREC_FP16>(a, num_cu, s);
+}
+
+}  // namespace sand

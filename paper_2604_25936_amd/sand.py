@@ -1,0 +1,220 @@
+"""ctypes binding of the SAND C ABI (include/sand.h).
+
+Argument marshalling only: every step of a query runs in the gfx950 kernels
+of ``_lib/libsand.so``. Torch supplies device memory and the current HIP
+stream. There is no fallback: if the library is missing, every entry point
+raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsand.so")
+
+OK, ERR_INVALID, ERR_FORMAT, ERR_NOMEM, ERR_DEVICE, ERR_BUDGET, ERR_UNSUPPORTED, ERR_TIMEOUT = range(8)
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+MODES = {"adaptive": 0, "full": 1, "forced": 2}
+
+
+class SandError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+class QueryOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("forced_depth", ctypes.c_void_p), ("depth_out", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("t_copied", ctypes.c_double), ("n", ctypes.c_int64),
+                ("batch_size", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"SAND library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, SZ, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_uint64
+        sig = {
+            "sand_query_opts_init": (None, [P]),
+            "sand_load_model": (I32, [P, SZ, ctypes.c_int, ctypes.POINTER(P)]),
+            "sand_free_model": (None, [P]),
+            "sand_model_info": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+            "sand_build_depthmap": (I32, [P, P, I32, P, ctypes.POINTER(P)]),
+            "sand_free_depthmap": (None, [P]),
+            "sand_query_workspace_size": (SZ, [I64]),
+            "sand_query": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P]),
+            "sand_query_grad": (I32, [P, P, P, I64, P, P, P, ctypes.POINTER(QueryOpts), P]),
+            "sand_server_create": (I32, [ctypes.c_int, SZ, I32, I32, ctypes.POINTER(P)]),
+            "sand_server_submit": (I32, [P, P, P, P, I64, P, ctypes.POINTER(U64)]),
+            "sand_server_wait": (I32, [P, U64, ctypes.c_double, ctypes.POINTER(ReqStats)]),
+            "sand_server_destroy": (None, [P]),
+            "sand_status_str": (ctypes.c_char_p, [I32]),
+            "sand_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status, what=""):
+    if status != OK:
+        msg = library().sand_last_error().decode(errors="replace")
+        raise SandError(status, msg or what)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Model:
+    """A T-MLP uploaded to one GPU (sand_load_model)."""
+
+    def __init__(self, blob, device=0):
+        blob = bytes(blob)
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(library().sand_load_model(buf, len(blob), device, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        L, W = ctypes.c_int32(), ctypes.c_int32()
+        _check(library().sand_model_info(h, ctypes.byref(L), ctypes.byref(W)))
+        self.L, self.W = L.value, W.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("model has been freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.sand_free_model(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+class DepthMap:
+    """A dense R^3 network-depth map for one model (sand_build_depthmap)."""
+
+    def __init__(self, model, depth, far=None):
+        depth = np.ascontiguousarray(depth, dtype=np.uint8)
+        if depth.ndim != 3 or not (depth.shape[0] == depth.shape[1] == depth.shape[2]):
+            raise ValueError("depth map must be a cube [R, R, R]")
+        farp = None
+        if far is not None:
+            far = np.ascontiguousarray(far, dtype=np.float32)
+            if far.shape != depth.shape:
+                raise ValueError("far values must match the map's shape")
+            farp = far.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(library().sand_build_depthmap(model.handle, depth.ctypes.data_as(ctypes.c_void_p),
+                                             depth.shape[0], farp, ctypes.byref(h)))
+        self._h = h
+        self.model = model
+        self.R = depth.shape[0]
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("depth map has been freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.sand_free_depthmap(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+def load_model(blob, device=0):
+    return Model(blob, device)
+
+
+def build_depthmap(model, depth, far=None):
+    return DepthMap(model, depth, far)
+
+
+def query_workspace_size(n):
+    return int(library().sand_query_workspace_size(int(n)))
+
+
+def _opts(precision, mode, max_depth, forced_depth, depth_out, workspace):
+    o = QueryOpts()
+    library().sand_query_opts_init(ctypes.byref(o))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.max_depth = int(max_depth)
+    o.forced_depth = None if forced_depth is None else forced_depth.data_ptr()
+    o.depth_out = None if depth_out is None else depth_out.data_ptr()
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
+
+
+def _check_points(xyz):
+    import torch
+    if xyz.dtype != torch.float32 or xyz.dim() != 2 or xyz.shape[1] != 3:
+        raise ValueError("xyz must be a float32 tensor of shape [n, 3]")
+    if not xyz.is_contiguous():
+        raise ValueError("xyz must be contiguous")
+
+
+def query(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_depth=0,
+          forced_depth=None, depth_out=None, workspace=None, stream=None):
+    """Signed distances of points ``xyz`` (float32 [n, 3] on the model's GPU)."""
+    import torch
+    _check_points(xyz)
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace)
+    _check(library().sand_query(model.handle, None if dmap is None else dmap.handle, _ptr(xyz), n,
+                                _ptr(out), ctypes.byref(o), _stream(stream)))
+    return out
+
+
+def query_grad(model, dmap, xyz, dy=None, sdf_out=None, grad_out=None, precision="fp32",
+               mode="adaptive", max_depth=0, forced_depth=None, depth_out=None, workspace=None,
+               stream=None):
+    """Input gradient dy * d y_{d(x)} / dx, float32 [n, 3]; also fills sdf_out if given."""
+    import torch
+    _check_points(xyz)
+    n = xyz.shape[0]
+    if grad_out is None:
+        grad_out = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace)
+    _check(library().sand_query_grad(model.handle, None if dmap is None else dmap.handle, _ptr(xyz),
+                                     n, _ptr(dy), _ptr(sdf_out), _ptr(grad_out), ctypes.byref(o),
+                                     _stream(stream)))
+    return grad_out

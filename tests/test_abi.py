@@ -1,0 +1,114 @@
+"""The C ABI library loads, exports what include/sand.h declares, and rejects
+bad arguments on the host before touching a device (CPU only)."""
+
+import ctypes
+import os
+import re
+import struct
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2604_25936_amd import sand
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sand.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sand_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = sand.library()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), f"{name} not exported"
+
+
+def test_status_strings():
+    lib = sand.library()
+    for s in range(8):
+        assert lib.sand_status_str(s)
+    assert lib.sand_status_str(99) == b"unknown status"
+
+
+def _load(blob, device=0):
+    h = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    st = sand.library().sand_load_model(buf, len(blob), device, ctypes.byref(h))
+    return st, h
+
+
+def _blob(L=2, W=16, tails="mult"):
+    return bytearray(synth.write_blob(synth.siren_tmlp(1, L, W, tails=tails)))
+
+
+def test_blob_format_errors():
+    good = _blob()
+    cases = {
+        "magic": (lambda b: b.__setitem__(slice(0, 8), b"NOTSAND!"), sand.ERR_FORMAT),
+        "version": (lambda b: struct.pack_into("<I", b, 8, 2), sand.ERR_FORMAT),
+        "layers0": (lambda b: struct.pack_into("<I", b, 12, 0), sand.ERR_FORMAT),
+        "layers17": (lambda b: struct.pack_into("<I", b, 12, 17), sand.ERR_FORMAT),
+        "indim": (lambda b: struct.pack_into("<I", b, 20, 2), sand.ERR_FORMAT),
+        "tailkind": (lambda b: b.__setitem__(33, 7), sand.ERR_FORMAT),
+        "unused_tail": (lambda b: b.__setitem__(40, 1), sand.ERR_FORMAT),
+        "reserved": (lambda b: b.__setitem__(50, 1), sand.ERR_FORMAT),
+        "nan": (lambda b: struct.pack_into("<f", b, 64 + 8, float("nan")), sand.ERR_FORMAT),
+        "inf_omega": (lambda b: struct.pack_into("<f", b, 24, float("inf")), sand.ERR_FORMAT),
+    }
+    for name, (mutate, want) in cases.items():
+        b = bytearray(good)
+        mutate(b)
+        st, h = _load(b)
+        assert st == want, f"{name}: status {st}"
+        assert not h.value
+    st, _ = _load(good[:-4])
+    assert st == sand.ERR_FORMAT
+    st, _ = _load(good + b"\0\0\0\0")
+    assert st == sand.ERR_FORMAT
+    st, _ = _load(good[:32])
+    assert st == sand.ERR_FORMAT
+    wide = _blob(L=1, W=400)
+    st, _ = _load(wide)
+    assert st == sand.ERR_UNSUPPORTED
+    assert b"width" in sand.library().sand_last_error()
+
+
+def test_null_arguments():
+    lib = sand.library()
+    h = ctypes.c_void_p()
+    assert lib.sand_load_model(None, 10, 0, ctypes.byref(h)) == sand.ERR_INVALID
+    assert lib.sand_build_depthmap(None, None, 4, None, ctypes.byref(h)) == sand.ERR_INVALID
+    o = sand.QueryOpts()
+    lib.sand_query_opts_init(ctypes.byref(o))
+    assert o.precision == 0 and o.mode == 0 and o.max_depth == 0
+    assert lib.sand_query(None, None, None, 0, None, ctypes.byref(o), None) == sand.ERR_INVALID
+    assert lib.sand_model_info(None, None, None) == sand.ERR_INVALID
+
+
+def test_workspace_size():
+    ws = sand.query_workspace_size
+    assert ws(0) == 0 and ws(-5) == 0
+    assert ws(1) > 0
+    assert ws(4096) >= 4096 * 5
+    sizes = [ws(n) for n in (1, 100, 4096, 4097, 1 << 20, 134217728)]
+    assert sizes == sorted(sizes)
+    assert all(s % 256 == 0 for s in sizes)
+    assert ws(134217728) < 134217728 * 6
+
+
+def test_python_binding_argument_checks():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        sand._check_points(torch.zeros(5, 2))
+    with pytest.raises(ValueError):
+        sand._check_points(torch.zeros(5, 3, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        sand._check_points(torch.zeros(3, 5).t())
+    with pytest.raises(KeyError):
+        sand._opts("fp64", "adaptive", 0, None, None, None)
