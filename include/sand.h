@@ -142,6 +142,18 @@ sand_status sand_query(sand_model model, sand_depthmap map,
                        const float* xyz_dev, int64_t n, float* sdf_dev,
                        const sand_query_opts* opts, void* hip_stream);
 
+/* sand_query, instrumented: records HIP events on `hip_stream` between the
+ * phases, waits for the query to finish, and stores the device time of each
+ * phase in phase_ms (host float[5]): [0] depth lookup and histogram, [1]
+ * bucket scan, [2] permutation scatter, [3] T-MLP evaluation with the
+ * result scatter, [4] the whole query. Phases a mode skips (FULL runs only
+ * the T-MLP) read 0. Blocks the calling thread; meant for measurement.
+ * Errors as sand_query, plus SAND_ERR_INVALID for a null phase_ms. */
+sand_status sand_query_timed(sand_model model, sand_depthmap map,
+                             const float* xyz_dev, int64_t n, float* sdf_dev,
+                             const sand_query_opts* opts, void* hip_stream,
+                             float* phase_ms);
+
 /* Input gradient (surface normal direction) of the queried value with each
  * point's exit depth held fixed: grad_dev[i] = dy[i] * d y_{d(x_i)} / d x_i,
  * computed by reverse accumulation from the exit tail back through layers

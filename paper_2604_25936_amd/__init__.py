@@ -7,7 +7,7 @@ This package is the Python binding of that library.
 """
 
 from .sand import (Model, DepthMap, SandError, load_model, build_depthmap, query,
-                   query_grad, query_workspace_size, library, PRECISIONS, MODES)
+                   query_timed, query_grad, query_workspace_size, library, PRECISIONS, MODES)
 
 __all__ = ["Model", "DepthMap", "SandError", "load_model", "build_depthmap", "query",
-           "query_grad", "query_workspace_size", "library", "PRECISIONS", "MODES"]
+           "query_timed", "query_grad", "query_workspace_size", "library", "PRECISIONS", "MODES"]

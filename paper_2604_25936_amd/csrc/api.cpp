@@ -461,7 +461,10 @@ sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const f
 
 // Lookup + bucketing + T-MLP for n points. `ws` must hold workspace_layout(n).
 sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
-                        const sand_query_opts& o, char* ws, hipStream_t s) {
+                        const sand_query_opts& o, char* ws, hipStream_t s, hipEvent_t* ev) {
+  auto mark = [&](int i) {
+    if (ev && ev[i]) (void)hipEventRecord(ev[i], s);
+  };
   const int prec = o.precision;
   QueryArgs qa{};
   qa.m = m->args[prec];
@@ -472,7 +475,12 @@ sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_
   if (o.mode == SAND_FULL) {
     const int d = (o.max_depth > 0 && o.max_depth < m->L) ? o.max_depth : m->L;
     qa.full_depth = d;
+    mark(0);
+    mark(1);
+    mark(2);
+    mark(3);
     if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
+    mark(4);
     if (o.depth_out && (e = launch_fill_u8(o.depth_out, n, (uint8_t)d, s)) != hipSuccess)
       return device_fail(e, "depth fill launch");
     return SAND_OK;
@@ -485,16 +493,21 @@ sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_
   const uint8_t* map = dm ? dm->depth : nullptr;
   const float* far = dm ? dm->far : nullptr;
   const int R = dm ? dm->R : 2;
+  mark(0);
   if ((e = launch_lookup_count(xyz, n, map, R, far, o.forced_depth, o.mode, m->L, o.max_depth, depth,
                                sdf, counts, s)) != hipSuccess)
     return device_fail(e, "lookup launch");
+  mark(1);
   if ((e = launch_scan(counts, w.nblk, m->L, tmlp_tile_points(prec), plan, s)) != hipSuccess)
     return device_fail(e, "scan launch");
+  mark(2);
   if ((e = launch_scatter(depth, n, counts, perm, s)) != hipSuccess)
     return device_fail(e, "scatter launch");
+  mark(3);
   qa.perm = perm;
   qa.plan = plan;
   if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
+  mark(4);
   return SAND_OK;
 }
 
@@ -521,6 +534,45 @@ extern "C" sand_status sand_query(sand_model m, sand_depthmap dm, const float* x
   }
   st = run_forward(m, dm, xyz, n, sdf, o, ws, s);
   if (owned) (void)hipFreeAsync(ws, s);
+  return st;
+}
+
+extern "C" sand_status sand_query_timed(sand_model m, sand_depthmap dm, const float* xyz,
+                                        int64_t n, float* sdf, const sand_query_opts* opts,
+                                        void* stream, float* phase_ms) {
+  if (!phase_ms) return fail(SAND_ERR_INVALID, "sand_query_timed: null phase_ms");
+  sand_query_opts o;
+  if (opts) o = *opts; else sand_query_opts_init(&o);
+  sand_status st = check_query("sand_query_timed", m, dm, xyz, n, sdf, o);
+  for (int i = 0; i < 5; ++i) phase_ms[i] = 0.0f;
+  if (st != SAND_OK || n == 0) return st;
+  DeviceGuard guard(m->device);
+  if (!guard.ok) return fail(SAND_ERR_DEVICE, "sand_query_timed: cannot select device");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t ev[5] = {};
+  for (int i = 0; i < 5; ++i)
+    if (hipEventCreate(&ev[i]) != hipSuccess) {
+      for (int k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
+      return fail(SAND_ERR_DEVICE, "sand_query_timed: event creation");
+    }
+  char* ws = (char*)o.workspace;
+  bool owned = false;
+  if (o.mode != SAND_FULL && !ws) {
+    if (hipMallocAsync((void**)&ws, workspace_layout(n).total, s) != hipSuccess) {
+      for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+      return fail(SAND_ERR_NOMEM, "sand_query_timed: scratch");
+    }
+    owned = true;
+  }
+  st = run_forward(m, dm, xyz, n, sdf, o, ws, s, ev);
+  if (owned) (void)hipFreeAsync(ws, s);
+  if (st == SAND_OK) {
+    hipError_t e = hipEventSynchronize(ev[4]);
+    if (e != hipSuccess) st = device_fail(e, "sand_query_timed: wait");
+    for (int i = 0; i < 4 && st == SAND_OK; ++i) (void)hipEventElapsedTime(&phase_ms[i], ev[i], ev[i + 1]);
+    if (st == SAND_OK) (void)hipEventElapsedTime(&phase_ms[4], ev[0], ev[4]);
+  }
+  for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
   return st;
 }
 

@@ -44,7 +44,11 @@ WorkspaceLayout workspace_layout(int64_t n);
 
 sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const float* xyz,
                         int64_t n, const void* out, const sand_query_opts& o);
+// Optional HIP events recorded between the forward phases (any may be null):
+// ev[0] before the lookup, ev[1] after it, ev[2] after the scan, ev[3] after
+// the scatter, ev[4] after the T-MLP.
 sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
-                        const sand_query_opts& o, char* ws, hipStream_t s);
+                        const sand_query_opts& o, char* ws, hipStream_t s,
+                        hipEvent_t* ev = nullptr);
 
 }  // namespace sand

@@ -60,6 +60,8 @@ def library():
             "sand_free_depthmap": (None, [P]),
             "sand_query_workspace_size": (SZ, [I64]),
             "sand_query": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P]),
+            "sand_query_timed": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P,
+                                       ctypes.POINTER(ctypes.c_float)]),
             "sand_query_grad": (I32, [P, P, P, I64, P, P, P, ctypes.POINTER(QueryOpts), P]),
             "sand_server_create": (I32, [ctypes.c_int, SZ, I32, I32, ctypes.POINTER(P)]),
             "sand_server_submit": (I32, [P, P, P, P, I64, P, ctypes.POINTER(U64)]),
@@ -202,6 +204,23 @@ def query(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_dep
     _check(library().sand_query(model.handle, None if dmap is None else dmap.handle, _ptr(xyz), n,
                                 _ptr(out), ctypes.byref(o), _stream(stream)))
     return out
+
+
+def query_timed(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_depth=0,
+                forced_depth=None, depth_out=None, workspace=None, stream=None):
+    """query() that waits and returns (out, phase_ms): device milliseconds of
+    [lookup, scan, scatter, t-mlp, whole query] measured with HIP events."""
+    import torch
+    _check_points(xyz)
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace)
+    ms = (ctypes.c_float * 5)()
+    _check(library().sand_query_timed(model.handle, None if dmap is None else dmap.handle,
+                                      _ptr(xyz), n, _ptr(out), ctypes.byref(o), _stream(stream),
+                                      ms))
+    return out, [float(v) for v in ms]
 
 
 def query_grad(model, dmap, xyz, dy=None, sdf_out=None, grad_out=None, precision="fp32",
