@@ -154,6 +154,12 @@ sand_status sand_query_timed(sand_model model, sand_depthmap map,
                              const sand_query_opts* opts, void* hip_stream,
                              float* phase_ms);
 
+/* Bytes of device scratch sand_query_grad needs for n points at the given
+ * precision (the query scratch plus a per-workgroup stash of the forward
+ * pass's cosines); 0 for n <= 0, a null model or a bad precision. */
+size_t sand_query_grad_workspace_size(sand_model model, int64_t n,
+                                      int32_t precision);
+
 /* Input gradient (surface normal direction) of the queried value with each
  * point's exit depth held fixed: grad_dev[i] = dy[i] * d y_{d(x_i)} / d x_i,
  * computed by reverse accumulation from the exit tail back through layers
@@ -161,6 +167,7 @@ sand_status sand_query_timed(sand_model model, sand_depthmap map,
  *  dy_dev:   device float32 [n] upstream gradient, or NULL for all ones.
  *  sdf_dev:  device float32 [n] or NULL; receives the forward values.
  *  grad_dev: device float32 [n][3].
+ *  opts.workspace, when given, must hold sand_query_grad_workspace_size.
  * Other arguments and errors as sand_query. */
 sand_status sand_query_grad(sand_model model, sand_depthmap map,
                             const float* xyz_dev, int64_t n,

@@ -291,6 +291,63 @@ std::vector<char> pack(const Blob& B, int prec, int WP) {
   return buf;
 }
 
+// Adjoint data of one precision: transposed chunks of layers 2..L (rows =
+// units of layer j-1, K = units of layer j in the permuted order, values
+// omega_j W_j[k][row]) followed by the tails of layer j-1 (layout in
+// sand_internal.h, without the bias step).
+std::vector<char> pack_bwd(const Blob& B, int prec, int WP) {
+  const Geo G(prec, WP);
+  const int W = B.W;
+  const size_t chb = (size_t)G.KS * 64 * G.VB + G.BM * 8;
+  std::vector<char> buf((size_t)(B.L - 1) * G.RB * chb, 0);
+  const double om = B.om[1];
+  for (int jl = 2; jl <= B.L; ++jl) {
+    const float* Wj = B.Wm[jl - 1];
+    for (int rb = 0; rb < G.RB; ++rb) {
+      char* ch = buf.data() + ((size_t)(jl - 2) * G.RB + rb) * chb;
+      for (int s = 0; s < G.KS; ++s)
+        for (int l = 0; l < 64; ++l) {
+          if (prec == PREC_FP32) {
+            const int m = l & 15, g = l >> 4;
+            const int ui = 16 * rb + m, uo = 16 * (s >> 2) + 4 * g + (s & 3);
+            const double v = (ui < W && uo < W) ? om * (double)Wj[(size_t)uo * W + ui] : 0.0;
+            ((float*)ch)[s * 64 + l] = (float)v;
+          } else {
+            const int m = l & 31, h = l >> 5, ui = 32 * rb + m;
+            uint16_t* A = (uint16_t*)(ch + ((size_t)s * 64 + l) * 16);
+            for (int p = 0; p < 8; ++p) {
+              const int uo = 16 * s + 8 * (p >> 2) + 4 * h + (p & 3);
+              const double v = (ui < W && uo < W) ? om * (double)Wj[(size_t)uo * W + ui] : 0.0;
+              A[p] = prec == PREC_BF16 ? to_bf16((float)v) : to_f16((float)v);
+            }
+          }
+        }
+      float* t = (float*)(ch + (size_t)G.KS * 64 * G.VB);
+      for (int i = 0; i < G.BM; ++i) {
+        const int u = G.BM * rb + i;
+        t[i] = u < W ? B.a0[jl - 2][u] : 0.0f;
+        t[G.BM + i] = (u < W && B.a1[jl - 2]) ? B.a1[jl - 2][u] : 0.0f;
+      }
+    }
+  }
+  return buf;
+}
+
+// omega_1 W_1 rows ([WP][4], last entry 0) and the tail table [L][2][WP].
+std::vector<char> pack_grad_tables(const Blob& B, int WP) {
+  std::vector<char> buf((size_t)WP * 16 + (size_t)B.L * 2 * WP * 4, 0);
+  float* w1 = (float*)buf.data();
+  for (int u = 0; u < B.W; ++u)
+    for (int k = 0; k < 3; ++k) w1[u * 4 + k] = (float)((double)B.om[0] * B.Wm[0][u * 3 + k]);
+  float* t = (float*)(buf.data() + (size_t)WP * 16);
+  for (int l = 0; l < B.L; ++l)
+    for (int u = 0; u < B.W; ++u) {
+      t[(size_t)l * 2 * WP + u] = B.a0[l][u];
+      t[(size_t)l * 2 * WP + WP + u] = B.a1[l] ? B.a1[l][u] : 0.0f;
+    }
+  return buf;
+}
+
 }  // namespace
 
 extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int device,
@@ -306,10 +363,15 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
     return fail(SAND_ERR_INVALID, "sand_load_model: device %d not available (%d devices)", device,
                 ndev);
   const int WP = padded_width(B.W);
-  std::vector<char> packs[3];
-  size_t offs[3], total = 0;
+  // forward packs (3 precisions), adjoint packs (3), then the FP32 tables
+  std::vector<char> packs[7];
+  size_t offs[7], total = 0;
   for (int p = 0; p < 3; ++p) {
     packs[p] = pack(B, p, WP);
+    packs[3 + p] = pack_bwd(B, p, WP);
+  }
+  packs[6] = pack_grad_tables(B, WP);
+  for (int p = 0; p < 7; ++p) {
     offs[p] = total;
     total += (packs[p].size() + 255) & ~(size_t)255;
   }
@@ -321,7 +383,8 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
   char* dev = nullptr;
   e = hipMalloc((void**)&dev, total);
   if (e != hipSuccess) return fail(SAND_ERR_NOMEM, "sand_load_model: %zu device bytes", total);
-  for (int p = 0; p < 3; ++p) {
+  for (int p = 0; p < 7; ++p) {
+    if (packs[p].empty()) continue;
     e = hipMemcpy(dev + offs[p], packs[p].data(), packs[p].size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(dev);
@@ -336,6 +399,9 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
   m->num_cu = num_cu;
   m->dev = dev;
   m->bytes = total;
+  for (int p = 0; p < 3; ++p) m->bwd[p] = dev + offs[3 + p];
+  m->w1t = (const float*)(dev + offs[6]);
+  m->tails = (const float*)(dev + offs[6] + (size_t)WP * 16);
   for (int p = 0; p < 3; ++p) {
     ModelArgs& a = m->args[p];
     std::memset(&a, 0, sizeof(a));
@@ -459,6 +525,42 @@ sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const f
   return SAND_OK;
 }
 
+size_t grad_stash_bytes(sand_model m, int prec) {
+  return (size_t)m->num_cu * adjoint_stash_bytes_per_wg(prec, m->WP, m->L);
+}
+
+sand_status run_bucketing(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
+                          float* grad, const sand_query_opts& o, char* ws, hipStream_t s,
+                          int tile_q, hipEvent_t* ev, const int32_t** perm_out,
+                          const Plan** plan_out) {
+  auto mark = [&](int i) {
+    if (ev && ev[i]) (void)hipEventRecord(ev[i], s);
+  };
+  const WorkspaceLayout w = workspace_layout(n);
+  uint8_t* depth = o.depth_out ? o.depth_out : (uint8_t*)(ws + w.depth);
+  int32_t* perm = (int32_t*)(ws + w.perm);
+  int32_t* counts = (int32_t*)(ws + w.counts);
+  Plan* plan = (Plan*)(ws + w.plan);
+  const uint8_t* map = dm ? dm->depth : nullptr;
+  const float* far = dm ? dm->far : nullptr;
+  const int R = dm ? dm->R : 2;
+  hipError_t e;
+  mark(0);
+  if ((e = launch_lookup_count(xyz, n, map, R, far, o.forced_depth, o.mode, m->L, o.max_depth, depth,
+                               sdf, grad, counts, s)) != hipSuccess)
+    return device_fail(e, "lookup launch");
+  mark(1);
+  if ((e = launch_scan(counts, w.nblk, m->L, tile_q, plan, s)) != hipSuccess)
+    return device_fail(e, "scan launch");
+  mark(2);
+  if ((e = launch_scatter(depth, n, counts, perm, s)) != hipSuccess)
+    return device_fail(e, "scatter launch");
+  mark(3);
+  *perm_out = perm;
+  *plan_out = plan;
+  return SAND_OK;
+}
+
 // Lookup + bucketing + T-MLP for n points. `ws` must hold workspace_layout(n).
 sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
                         const sand_query_opts& o, char* ws, hipStream_t s, hipEvent_t* ev) {
@@ -475,37 +577,16 @@ sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_
   if (o.mode == SAND_FULL) {
     const int d = (o.max_depth > 0 && o.max_depth < m->L) ? o.max_depth : m->L;
     qa.full_depth = d;
-    mark(0);
-    mark(1);
-    mark(2);
-    mark(3);
+    for (int i = 0; i < 4; ++i) mark(i);
     if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
     mark(4);
     if (o.depth_out && (e = launch_fill_u8(o.depth_out, n, (uint8_t)d, s)) != hipSuccess)
       return device_fail(e, "depth fill launch");
     return SAND_OK;
   }
-  const WorkspaceLayout w = workspace_layout(n);
-  uint8_t* depth = o.depth_out ? o.depth_out : (uint8_t*)(ws + w.depth);
-  int32_t* perm = (int32_t*)(ws + w.perm);
-  int32_t* counts = (int32_t*)(ws + w.counts);
-  Plan* plan = (Plan*)(ws + w.plan);
-  const uint8_t* map = dm ? dm->depth : nullptr;
-  const float* far = dm ? dm->far : nullptr;
-  const int R = dm ? dm->R : 2;
-  mark(0);
-  if ((e = launch_lookup_count(xyz, n, map, R, far, o.forced_depth, o.mode, m->L, o.max_depth, depth,
-                               sdf, counts, s)) != hipSuccess)
-    return device_fail(e, "lookup launch");
-  mark(1);
-  if ((e = launch_scan(counts, w.nblk, m->L, tmlp_tile_points(prec), plan, s)) != hipSuccess)
-    return device_fail(e, "scan launch");
-  mark(2);
-  if ((e = launch_scatter(depth, n, counts, perm, s)) != hipSuccess)
-    return device_fail(e, "scatter launch");
-  mark(3);
-  qa.perm = perm;
-  qa.plan = plan;
+  sand_status st = run_bucketing(m, dm, xyz, n, sdf, nullptr, o, ws, s, tmlp_tile_points(prec), ev,
+                                 &qa.perm, &qa.plan);
+  if (st != SAND_OK) return st;
   if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
   mark(4);
   return SAND_OK;
@@ -576,9 +657,62 @@ extern "C" sand_status sand_query_timed(sand_model m, sand_depthmap dm, const fl
   return st;
 }
 
+extern "C" size_t sand_query_grad_workspace_size(sand_model m, int64_t n, int32_t precision) {
+  if (!m || n <= 0 || precision < 0 || precision > 2) return 0;
+  return workspace_layout(n).total + grad_stash_bytes(m, precision);
+}
+
 extern "C" sand_status sand_query_grad(sand_model m, sand_depthmap dm, const float* xyz, int64_t n,
                                        const float* dy, float* sdf, float* grad,
                                        const sand_query_opts* opts, void* stream) {
-  (void)m; (void)dm; (void)xyz; (void)n; (void)dy; (void)sdf; (void)grad; (void)opts; (void)stream;
-  return fail(SAND_ERR_UNSUPPORTED, "sand_query_grad: not built yet");
+  sand_query_opts o;
+  if (opts) o = *opts; else sand_query_opts_init(&o);
+  sand_status st = check_query("sand_query_grad", m, dm, xyz, n, grad, o);
+  if (st != SAND_OK || n == 0) return st;
+  const size_t need = workspace_layout(n).total + grad_stash_bytes(m, o.precision);
+  if (o.workspace && o.workspace_bytes < need)
+    return fail(SAND_ERR_INVALID, "sand_query_grad: workspace of %zu bytes, need %zu",
+                o.workspace_bytes, need);
+  DeviceGuard guard(m->device);
+  if (!guard.ok) return fail(SAND_ERR_DEVICE, "sand_query_grad: cannot select device");
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)o.workspace;
+  bool owned = false;
+  if (!ws) {
+    if (hipMallocAsync((void**)&ws, need, s) != hipSuccess)
+      return fail(SAND_ERR_NOMEM, "sand_query_grad: scratch of %zu bytes", need);
+    owned = true;
+  }
+  const int prec = o.precision;
+  AdjointArgs aa{};
+  aa.q.m = m->args[prec];
+  aa.q.xyz = xyz;
+  aa.q.sdf = sdf;
+  aa.q.n = n;
+  aa.bwd = m->bwd[prec];
+  aa.w1t = m->w1t;
+  aa.tails = m->tails;
+  aa.dy = dy;
+  aa.grad = grad;
+  aa.stash = ws + workspace_layout(n).total;
+  aa.stash_wg = adjoint_stash_bytes_per_wg(prec, m->WP, m->L);
+  hipError_t e = hipSuccess;
+  if (o.mode == SAND_FULL) {
+    aa.q.full_depth = (o.max_depth > 0 && o.max_depth < m->L) ? o.max_depth : m->L;
+    if (o.depth_out) e = launch_fill_u8(o.depth_out, n, (uint8_t)aa.q.full_depth, s);
+    if (e != hipSuccess) st = device_fail(e, "depth fill launch");
+  } else {
+    st = run_bucketing(m, dm, xyz, n, sdf, grad, o, ws, s, tmlp_tile_points(prec), nullptr,
+                       &aa.q.perm, &aa.q.plan);
+  }
+  if (st == SAND_OK) {
+    int grid = m->num_cu;
+    if (o.mode == SAND_FULL) {
+      const int64_t tiles = (n + tmlp_tile_points(prec) - 1) / tmlp_tile_points(prec);
+      if (tiles < grid) grid = (int)tiles;
+    }
+    if ((e = launch_adjoint(prec, aa, grid, s)) != hipSuccess) st = device_fail(e, "adjoint launch");
+  }
+  if (owned) (void)hipFreeAsync(ws, s);
+  return st;
 }

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
     const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
     int R, const float* __restrict__ far, const uint8_t* __restrict__ forced,
     int mode, int L, int max_depth, uint8_t* __restrict__ depth,
-    float* __restrict__ sdf, int32_t* __restrict__ counts) {
+    float* __restrict__ sdf, float* __restrict__ grad, int32_t* __restrict__ counts) {
   __shared__ float sx[3 * kLookupThreads];
   __shared__ int hist[kBuckets];
   const int t = threadIdx.x;
@@ -93,7 +93,10 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
       }
       if (max_depth > 0 && d > max_depth) d = max_depth;
       depth[q] = (uint8_t)d;
-      if (d == 0) sdf[q] = (far != nullptr && cell >= 0) ? far[cell] : __builtin_nanf("");
+      if (d == 0) {
+        if (sdf) sdf[q] = (far != nullptr && cell >= 0) ? far[cell] : __builtin_nanf("");
+        if (grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
+      }
     }
     wave_histogram(d, valid, hist);
   }
@@ -217,11 +220,11 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
 
 hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map, int R,
                                const float* far, const uint8_t* forced, int mode, int L,
-                               int max_depth, uint8_t* depth, float* sdf, int32_t* counts,
-                               hipStream_t s) {
+                               int max_depth, uint8_t* depth, float* sdf, float* grad,
+                               int32_t* counts, hipStream_t s) {
   const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
   hipLaunchKernelGGL(k_lookup_count, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, xyz,
-                     n, map, R, far, forced, mode, L, max_depth, depth, sdf, counts);
+                     n, map, R, far, forced, mode, L, max_depth, depth, sdf, grad, counts);
   return hipGetLastError();
 }
 

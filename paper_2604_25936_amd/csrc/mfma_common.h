@@ -1,0 +1,181 @@
+// MFMA geometry and LDS streaming shared by the forward (tmlp.hip) and the
+// adjoint (adjoint.hip) T-MLP kernels on gfx950.
+#pragma once
+
+#include "sand_internal.h"
+
+namespace sand {
+namespace mfma {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Per-precision MFMA geometry. For lane l: `col` is its point within the
+// wavefront's block, `grp` its row group; accumulator register e holds one
+// unit of the current output block (see tail_row and put).
+template <int PREC>
+struct Tr;
+
+template <>
+struct Tr<PREC_FP32> {
+  using V = float;
+  using Acc = f32x4;
+  static constexpr int BM = 16;   // units per output block
+  static constexpr int NQ = 16;   // points per wavefront
+  static constexpr int NR = 4;    // accumulator registers per lane
+  static constexpr int SPB = 4;   // K steps per block of input units
+  static constexpr int VB = 4;    // A-operand bytes per lane per K step
+  static constexpr int L1S = 1;   // layer-1 MFMA steps
+  __device__ __forceinline__ static int col(int lane) { return lane & 15; }
+  __device__ __forceinline__ static int grp(int lane) { return lane >> 4; }
+  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) { return mma(a, b, c); }
+  __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
+    return g == 0 ? x : g == 1 ? y : g == 2 ? z : 1.0f;
+  }
+  __device__ __forceinline__ static V bias_b(int g) { return g == 0 ? 1.0f : 0.0f; }
+  // offset (in floats) of the 4 tail rows that registers 4i..4i+3 hold
+  __device__ __forceinline__ static int tail_row(int i, int g) { return 4 * g; }
+  template <int KS>
+  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
+    act[4 * rb + e] = v;
+  }
+  // store a block's NR values (in register order) as next-layer B operands
+  template <int KS>
+  __device__ __forceinline__ static void store(V (&act)[KS], int rb, const float (&h)[NR]) {
+#pragma unroll
+    for (int e = 0; e < NR; ++e) act[4 * rb + e] = h[e];
+  }
+  __device__ __forceinline__ static float lane_sum(float v) {
+    v += __shfl_xor(v, 16);
+    return v + __shfl_xor(v, 32);
+  }
+};
+
+template <int PREC>
+struct Tr16 {
+  using Acc = f32x16;
+  // store a block's NR values (in register order) as next-layer B operands,
+  // each 8-wide vector built fresh so no earlier contents stay live
+  template <class V, class E, int KS>
+  __device__ __forceinline__ static void store16(V (&act)[KS], int rb, const float (&h)[16]) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      V v;
+#pragma unroll
+      for (int p = 0; p < 8; ++p) v[p] = (E)h[8 * q + p];
+      act[2 * rb + q] = v;
+    }
+  }
+  static constexpr int BM = 32;
+  static constexpr int NQ = 32;
+  static constexpr int NR = 16;
+  static constexpr int SPB = 2;
+  static constexpr int VB = 16;
+  static constexpr int L1S = 2;
+  __device__ __forceinline__ static int col(int lane) { return lane & 31; }
+  __device__ __forceinline__ static int grp(int lane) { return lane >> 5; }
+  __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
+    return step == 0 ? (g == 0 ? x : y) : (g == 0 ? z : 1.0f);
+  }
+  __device__ __forceinline__ static int tail_row(int i, int g) { return 8 * i + 4 * g; }
+  __device__ __forceinline__ static float lane_sum(float v) { return v + __shfl_xor(v, 32); }
+};
+
+template <>
+struct Tr<PREC_BF16> : Tr16<PREC_BF16> {
+  using V = bf16x8;
+  using E = __bf16;
+  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static V bias_b(int g) {
+    const __bf16 one = (__bf16)(g == 0 ? 1.0f : 0.0f), z = (__bf16)0.0f;
+    return V{one, one, z, z, z, z, z, z};
+  }
+  template <int KS>
+  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
+    act[2 * rb + (e >> 3)][e & 7] = (__bf16)v;
+  }
+  template <int KS>
+  __device__ __forceinline__ static void store(V (&act)[KS], int rb, const float (&h)[16]) {
+    store16<V, E, KS>(act, rb, h);
+  }
+};
+
+template <>
+struct Tr<PREC_FP16> : Tr16<PREC_FP16> {
+  using V = f16x8;
+  using E = _Float16;
+  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static V bias_b(int g) {
+    const _Float16 one = (_Float16)(g == 0 ? 1.0f : 0.0f), z = (_Float16)0.0f;
+    return V{one, one, z, z, z, z, z, z};
+  }
+  template <int KS>
+  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
+    act[2 * rb + (e >> 3)][e & 7] = (_Float16)v;
+  }
+  template <int KS>
+  __device__ __forceinline__ static void store(V (&act)[KS], int rb, const float (&h)[16]) {
+    store16<V, E, KS>(act, rb, h);
+  }
+};
+
+__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+
+template <int PREC, int WP>
+struct Cfg {
+  using T = Tr<PREC>;
+  static constexpr int NW = 8;
+  static constexpr int NT = NW * 64;
+  static constexpr int Q = NW * T::NQ;          // points per tile
+  static constexpr int RB = WP / T::BM;         // output blocks per layer
+  static constexpr int KS = RB * T::SPB;        // K steps of a hidden product
+  // forward chunk: KS weight steps + 1 bias step, then tail weights
+  static constexpr int TAIL_OFF = (KS + 1) * 64 * T::VB;
+  static constexpr int CH = TAIL_OFF + T::BM * 8;
+  // adjoint chunk (transposed weights, no bias), then tail weights
+  static constexpr int TAIL_OFF_B = KS * 64 * T::VB;
+  static constexpr int CH_B = TAIL_OFF_B + T::BM * 8;
+  static constexpr int L1C = T::L1S * 256 + T::BM * 8;   // layer-1 chunk bytes
+  static constexpr int L1B = RB * L1C;
+  static constexpr int LDS = 2 * CH + L1B;
+  static_assert(CH % 16 == 0 && CH_B % 16 == 0 && L1B % 16 == 0,
+                "chunks are whole 16-byte pieces");
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Start copying one chunk of BYTES bytes from global memory into an LDS slot
+// without passing through registers: each wavefront-wide load moves 64
+// pieces of 16 bytes to 1 KB of LDS. Completion is awaited (vmcnt) before the
+// next workgroup barrier.
+template <int BYTES, int NW>
+__device__ __forceinline__ void load_chunk(const char* __restrict__ src, char* dst, int wave,
+                                           int lane) {
+  constexpr int NP = BYTES / 16;
+  constexpr int WL = (NP + 64 * NW - 1) / (64 * NW);
+#pragma unroll
+  for (int k = 0; k < WL; ++k) {
+    const int q = k * NW + wave;
+    const int piece = q * 64 + lane;
+    if (q * 64 < NP && piece < NP)
+      __builtin_amdgcn_global_load_lds((const void*)(src + piece * 16), (lds_void*)(dst + q * 1024),
+                                       16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void wait_chunk() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+}  // namespace mfma
+}  // namespace sand

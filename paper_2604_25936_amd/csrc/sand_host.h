@@ -13,6 +13,11 @@ struct sand_model_s {
   char* dev = nullptr;        // one allocation holding the three packed precisions
   size_t bytes = 0;
   sand::ModelArgs args[3];    // indexed by sand_precision
+  // input-gradient data (same allocation): transposed chunks per precision,
+  // omega_1 W_1 rows and the tail table
+  const char* bwd[3] = {nullptr, nullptr, nullptr};
+  const float* w1t = nullptr;
+  const float* tails = nullptr;
 };
 
 struct sand_depthmap_s {
@@ -41,9 +46,17 @@ struct WorkspaceLayout {
   int64_t nblk;
 };
 WorkspaceLayout workspace_layout(int64_t n);
+size_t grad_stash_bytes(sand_model m, int prec);
 
 sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const float* xyz,
                         int64_t n, const void* out, const sand_query_opts& o);
+// Lookup, histogram, scan and scatter (ADAPTIVE / FORCED). Far-field points
+// get their value in sdf (if non-null) and a zero gradient in grad (if
+// non-null). On return perm/plan describe the depth buckets.
+sand_status run_bucketing(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
+                          float* grad, const sand_query_opts& o, char* ws, hipStream_t s,
+                          int tile_q, hipEvent_t* ev, const int32_t** perm, const Plan** plan);
+
 // Optional HIP events recorded between the forward phases (any may be null):
 // ev[0] before the lookup, ev[1] after it, ev[2] after the scan, ev[3] after
 // the scatter, ev[4] after the T-MLP.

@@ -81,11 +81,23 @@ struct QueryArgs {
   int full_depth;          // FULL mode: the depth every point runs to
 };
 
+// Everything one input-gradient launch needs.
+struct AdjointArgs {
+  QueryArgs q;             // forward chunks, points, optional sdf out, plan
+  const char* bwd;         // transposed-weight chunks of layers 2..L
+  const float* w1t;        // [WP][4]: omega_1 * W_1[u][0..2], 0
+  const float* tails;      // [L][2][WP]: a0, a1 of every layer
+  const float* dy;         // [n] upstream gradient or null (ones)
+  float* grad;             // [n][3]
+  char* stash;             // per-workgroup cosine stash
+  size_t stash_wg;         // stash bytes per workgroup
+};
+
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map,
                                int R, const float* far, const uint8_t* forced,
                                int mode, int L, int max_depth, uint8_t* depth,
-                               float* sdf, int32_t* counts, hipStream_t s);
+                               float* sdf, float* grad, int32_t* counts, hipStream_t s);
 hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q,
                        Plan* plan, hipStream_t s);
 hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
@@ -93,6 +105,8 @@ hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 
 int tmlp_tile_points(int prec);
+size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L);
+hipError_t launch_adjoint(int prec, const AdjointArgs& a, int grid, hipStream_t s);
 hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s);
 
 }  // namespace sand

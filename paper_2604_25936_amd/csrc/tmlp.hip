@@ -30,149 +30,13 @@
 // The grid is persistent (one workgroup per CU) and strides over tiles,
 // which the plan orders deepest bucket first.
 
-#include "sand_internal.h"
+#include "mfma_common.h"
 
 namespace sand {
 
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-// Per-precision MFMA geometry. For lane l: `col` is its point within the
-// wavefront's block, `grp` its row group; accumulator register e holds one
-// unit of the current output block (see tail_row and put).
-template <int PREC>
-struct Tr;
-
-template <>
-struct Tr<PREC_FP32> {
-  using V = float;
-  using Acc = f32x4;
-  static constexpr int BM = 16;   // units per output block
-  static constexpr int NQ = 16;   // points per wavefront
-  static constexpr int NR = 4;    // accumulator registers per lane
-  static constexpr int SPB = 4;   // K steps per block of input units
-  static constexpr int VB = 4;    // A-operand bytes per lane per K step
-  static constexpr int L1S = 1;   // layer-1 MFMA steps
-  __device__ __forceinline__ static int col(int lane) { return lane & 15; }
-  __device__ __forceinline__ static int grp(int lane) { return lane >> 4; }
-  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) { return mma(a, b, c); }
-  __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
-    return g == 0 ? x : g == 1 ? y : g == 2 ? z : 1.0f;
-  }
-  __device__ __forceinline__ static V bias_b(int g) { return g == 0 ? 1.0f : 0.0f; }
-  // offset (in floats) of the 4 tail rows that registers 4i..4i+3 hold
-  __device__ __forceinline__ static int tail_row(int i, int g) { return 4 * g; }
-  template <int KS>
-  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
-    act[4 * rb + e] = v;
-  }
-  __device__ __forceinline__ static float lane_sum(float v) {
-    v += __shfl_xor(v, 16);
-    return v + __shfl_xor(v, 32);
-  }
-};
-
-template <int PREC>
-struct Tr16 {
-  using Acc = f32x16;
-  static constexpr int BM = 32;
-  static constexpr int NQ = 32;
-  static constexpr int NR = 16;
-  static constexpr int SPB = 2;
-  static constexpr int VB = 16;
-  static constexpr int L1S = 2;
-  __device__ __forceinline__ static int col(int lane) { return lane & 31; }
-  __device__ __forceinline__ static int grp(int lane) { return lane >> 5; }
-  __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-  }
-  __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
-    return step == 0 ? (g == 0 ? x : y) : (g == 0 ? z : 1.0f);
-  }
-  __device__ __forceinline__ static int tail_row(int i, int g) { return 8 * i + 4 * g; }
-  __device__ __forceinline__ static float lane_sum(float v) { return v + __shfl_xor(v, 32); }
-};
-
-template <>
-struct Tr<PREC_BF16> : Tr16<PREC_BF16> {
-  using V = bf16x8;
-  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-  }
-  __device__ __forceinline__ static V bias_b(int g) {
-    const __bf16 one = (__bf16)(g == 0 ? 1.0f : 0.0f), z = (__bf16)0.0f;
-    return V{one, one, z, z, z, z, z, z};
-  }
-  template <int KS>
-  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
-    act[2 * rb + (e >> 3)][e & 7] = (__bf16)v;
-  }
-};
-
-template <>
-struct Tr<PREC_FP16> : Tr16<PREC_FP16> {
-  using V = f16x8;
-  __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-  }
-  __device__ __forceinline__ static V bias_b(int g) {
-    const _Float16 one = (_Float16)(g == 0 ? 1.0f : 0.0f), z = (_Float16)0.0f;
-    return V{one, one, z, z, z, z, z, z};
-  }
-  template <int KS>
-  __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
-    act[2 * rb + (e >> 3)][e & 7] = (_Float16)v;
-  }
-};
-
-__device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
-
-template <int PREC, int WP>
-struct Cfg {
-  using T = Tr<PREC>;
-  static constexpr int NW = 8;
-  static constexpr int NT = NW * 64;
-  static constexpr int Q = NW * T::NQ;          // points per tile
-  static constexpr int RB = WP / T::BM;         // output blocks per layer
-  static constexpr int KS = RB * T::SPB;        // K steps of a hidden product
-  static constexpr int TAIL_OFF = (KS + 1) * 64 * T::VB;
-  static constexpr int CH = TAIL_OFF + T::BM * 8;
-  static constexpr int NP = CH / 16;                 // 16-byte pieces per chunk
-  static constexpr int WL = (NP + 64 * NW - 1) / (64 * NW);  // loads per wavefront
-  static constexpr int L1C = T::L1S * 256 + T::BM * 8;   // layer-1 chunk bytes
-  static constexpr int L1B = RB * L1C;
-  static constexpr int LDS = 2 * CH + L1B;
-  static_assert(CH % 16 == 0 && L1B % 16 == 0, "chunks are whole 16-byte pieces");
-};
-
-typedef __attribute__((address_space(3))) void lds_void;
-
-// Start copying one chunk from global memory into an LDS slot without
-// passing through registers: each wavefront-wide load moves 64 pieces of
-// 16 bytes to 1 KB of LDS. Completion is awaited (vmcnt) before the next
-// workgroup barrier.
-template <int PREC, int WP>
-__device__ __forceinline__ void load_chunk(const char* __restrict__ src, char* dst, int wave,
-                                           int lane) {
-  using C = Cfg<PREC, WP>;
-#pragma unroll
-  for (int k = 0; k < C::WL; ++k) {
-    const int q = k * C::NW + wave;
-    const int piece = q * 64 + lane;
-    if (q * 64 < C::NP && piece < C::NP)
-      __builtin_amdgcn_global_load_lds((const void*)(src + piece * 16), (lds_void*)(dst + q * 1024),
-                                       16, 0, 0);
-  }
-}
-
-__device__ __forceinline__ void wait_chunk() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+using namespace mfma;
 
 // Epilogue of one output block: sine, tail partial sums, pack for the next layer.
 template <int PREC, int KS>
@@ -213,16 +77,18 @@ __device__ __forceinline__ void pin_block(const typename Tr<PREC>::V (&out)[KS],
   }
 }
 
+// Add tail t_j = u0 * u1 to the running output (u0, u1 its two factors,
+// summed over the lanes that hold the point's units).
 template <int PREC>
-__device__ __forceinline__ float tail_value(float s0, float s1, float c0, float c1) {
+__device__ __forceinline__ float add_tail(float y, float s0, float s1, float c0, float c1) {
   using T = Tr<PREC>;
-  return (T::lane_sum(s0) + c0) * (T::lane_sum(s1) + c1);
+  return fmaf(T::lane_sum(s0) + c0, T::lane_sum(s1) + c1, y);
 }
 
 // One hidden layer: in -> out, streaming its RB chunks through the LDS ring.
 // c is the tile's running chunk index, nc its chunk count.
 template <int PREC, int WP>
-__device__ __forceinline__ float hidden_layer(const char* __restrict__ hidden, char* ring,
+__device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ hidden, char* ring,
                                               int wave, int lane, int g, int& c, int nc,
                                               const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
                                               typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
@@ -236,8 +102,8 @@ __device__ __forceinline__ float hidden_layer(const char* __restrict__ hidden, c
   for (int rb = 0; rb < C::RB; ++rb) {
     const bool pre = c + 1 < nc;
     if (pre)
-      load_chunk<PREC, WP>(hidden + (size_t)(c + 1) * C::CH, ring + ((c + 1) & 1) * C::CH, wave,
-                           lane);
+      load_chunk<C::CH, C::NW>(hidden + (size_t)(c + 1) * C::CH, ring + ((c + 1) & 1) * C::CH,
+                               wave, lane);
     const char* slot = ring + (c & 1) * C::CH;
     typename T::Acc acc = {};
 #pragma unroll
@@ -252,7 +118,7 @@ __device__ __forceinline__ float hidden_layer(const char* __restrict__ hidden, c
     __syncthreads();
     ++c;
   }
-  return tail_value<PREC>(s0, s1, c0, c1);
+  return add_tail<PREC>(y, s0, s1, c0, c1);
 }
 
 template <int PREC, int WP>
@@ -318,21 +184,21 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
       epilogue<PREC, C::KS>(ch + T::L1S * 256, g, rb, acc, actA, s0, s1);
       pin_block<PREC, C::KS>(actA, rb, s0, s1);
     }
-    float y = tail_value<PREC>(s0, s1, a.m.c0[0], a.m.c1[0]);
+    float y = add_tail<PREC>(0.0f, s0, s1, a.m.c0[0], a.m.c1[0]);
 
     const int nc = (d - 1) * C::RB;
     int c = 0;
     if (nc > 0) {
-      load_chunk<PREC, WP>(hidden, ring, wave, lane);
+      load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
       wait_chunk();
       __syncthreads();
     }
     for (int j = 2; j <= d; j += 2) {
-      y += hidden_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, actA, actB, a.m.c0[j - 1],
-                                  a.m.c1[j - 1]);
+      y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actA, actB, a.m.c0[j - 1],
+                                 a.m.c1[j - 1]);
       if (j + 1 > d) break;
-      y += hidden_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, actB, actA, a.m.c0[j],
-                                  a.m.c1[j]);
+      y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, a.m.c0[j],
+                                 a.m.c1[j]);
     }
     if (g == 0 && ok) a.sdf[gi] = y;
   }

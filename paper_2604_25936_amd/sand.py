@@ -59,6 +59,7 @@ def library():
             "sand_build_depthmap": (I32, [P, P, I32, P, ctypes.POINTER(P)]),
             "sand_free_depthmap": (None, [P]),
             "sand_query_workspace_size": (SZ, [I64]),
+            "sand_query_grad_workspace_size": (SZ, [P, I64, I32]),
             "sand_query": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P]),
             "sand_query_timed": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P,
                                        ctypes.POINTER(ctypes.c_float)]),
@@ -168,6 +169,11 @@ def build_depthmap(model, depth, far=None):
 
 def query_workspace_size(n):
     return int(library().sand_query_workspace_size(int(n)))
+
+
+def query_grad_workspace_size(model, n, precision="fp32"):
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return int(library().sand_query_grad_workspace_size(model.handle, int(n), p))
 
 
 def _opts(precision, mode, max_depth, forced_depth, depth_out, workspace):
