@@ -123,6 +123,7 @@ sand_status sand_model_info(sand_model model, int32_t* n_layers,
 sand_status sand_build_depthmap(sand_model model, const uint8_t* depth_host,
                                 int32_t R, const float* far_host,
                                 sand_depthmap* out);
+/* Free a map (before or after its model; queries using it must be done). */
 void sand_free_depthmap(sand_depthmap map);
 
 /* ---- queries ------------------------------------------------------------- */
@@ -195,6 +196,12 @@ typedef struct {
  * arriving while others run join the next launch), overlaps launches on
  * `n_streams` streams and copies results back. Precision as in
  * sand_query_opts (FP32, BF16 or FP16); mode is always ADAPTIVE.
+ * The device bytes a request holds (points, results, bucketing scratch:
+ * about 21 bytes per point) are reserved from a single arena of
+ * `hbm_budget_bytes` allocated at creation; requests are admitted first-in
+ * first-out, so a large request is never overtaken. Host buffers may be
+ * pageable; pinned buffers let the copies overlap with computation.
+ * n_streams: 1..16 concurrent batches.
  * A result is the same whether a request runs alone or batched. */
 sand_status sand_server_create(int device, size_t hbm_budget_bytes,
                                int32_t precision, int32_t n_streams,
@@ -210,7 +217,22 @@ sand_status sand_server_submit(sand_server server, sand_model model,
  * stats may be NULL. Each ticket can be waited for once. */
 sand_status sand_server_wait(sand_server server, uint64_t ticket,
                              double timeout_s, sand_req_stats* stats);
-/* Stop accepting requests, finish the admitted ones and free everything. */
+typedef struct {
+  size_t budget_bytes;         /* the HBM arena size given at creation */
+  size_t reserved_bytes;       /* held now by admitted requests */
+  size_t peak_reserved_bytes;  /* maximum ever held (never above the budget) */
+  uint64_t submitted;          /* requests accepted by sand_server_submit */
+  uint64_t completed;          /* requests whose results are in host memory */
+  uint64_t batches;            /* batched launches issued */
+  int32_t max_batch_requests;  /* most requests that shared one launch */
+  int32_t in_flight_batches;   /* batches on the device now */
+} sand_server_info;
+
+/* Counters of a running server. Errors: SAND_ERR_INVALID for null args. */
+sand_status sand_server_stats(sand_server server, sand_server_info* info);
+
+/* Stop accepting requests, finish everything admitted or queued, and free
+ * the server. Tickets not yet waited for become invalid. */
 void sand_server_destroy(sand_server server);
 
 /* ---- errors -------------------------------------------------------------- */

@@ -375,6 +375,8 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
     offs[p] = total;
     total += (packs[p].size() + 255) & ~(size_t)255;
   }
+  const size_t args_off = total;
+  total += 3 * ((sizeof(ModelArgs) + 255) & ~(size_t)255);
   DeviceGuard guard(device);
   if (!guard.ok) return fail(SAND_ERR_DEVICE, "sand_load_model: cannot select device %d", device);
   int num_cu = 0;
@@ -413,6 +415,16 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
       a.c0[i] = B.c0[i];
       a.c1[i] = B.c1[i];
     }
+  }
+  for (int p = 0; p < 3; ++p) {
+    char* dst = dev + args_off + p * ((sizeof(ModelArgs) + 255) & ~(size_t)255);
+    e = hipMemcpy(dst, &m->args[p], sizeof(ModelArgs), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(dev);
+      delete m;
+      return device_fail(e, "sand_load_model: upload");
+    }
+    m->args_dev[p] = (const ModelArgs*)dst;
   }
   *out = m;
   return SAND_OK;
@@ -469,6 +481,7 @@ extern "C" sand_status sand_build_depthmap(sand_model m, const uint8_t* depth_ho
   }
   sand_depthmap dm = new sand_depthmap_s();
   dm->model = m;
+  dm->device = m->device;
   dm->R = R;
   dm->depth = d;
   dm->far = f;
@@ -478,7 +491,7 @@ extern "C" sand_status sand_build_depthmap(sand_model m, const uint8_t* depth_ho
 
 extern "C" void sand_free_depthmap(sand_depthmap dm) {
   if (!dm) return;
-  DeviceGuard guard(dm->model->device);
+  DeviceGuard guard(dm->device);
   (void)hipFree(dm->depth);
   if (dm->far) (void)hipFree(dm->far);
   delete dm;

@@ -13,7 +13,9 @@
 //   3. k_scatter: per chunk again, each point's rank among equal depths
 //      (ballot + popcount below the lane) gives its slot in the permutation.
 // Point coordinates are read through LDS so that every global load of a
-// wavefront covers 256 contiguous bytes.
+// wavefront covers 256 contiguous bytes. Batched variants run the same
+// bodies for several queries in one launch (each lookup block belongs to
+// one query; one scan workgroup per query).
 
 #include "sand_internal.h"
 
@@ -51,8 +53,9 @@ __device__ __forceinline__ void wave_histogram(int d, bool valid, int* hist) {
   }
 }
 
-__global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
-    const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
+// Body of one lookup block: points [blk*4096, blk*4096 + 4096) of one query.
+__device__ __forceinline__ void lookup_block(
+    int64_t blk, const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
     int R, const float* __restrict__ far, const uint8_t* __restrict__ forced,
     int mode, int L, int max_depth, uint8_t* __restrict__ depth,
     float* __restrict__ sdf, float* __restrict__ grad, int32_t* __restrict__ counts) {
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
   __shared__ int hist[kBuckets];
   const int t = threadIdx.x;
   if (t < kBuckets) hist[t] = 0;
-  const int64_t base = (int64_t)blockIdx.x * kLookupChunk;
+  const int64_t base = blk * kLookupChunk;
   const int half = R >> 1;
   const float s = (float)half;
   for (int r = 0; r < kRounds; ++r) {
@@ -101,7 +104,16 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
     wave_histogram(d, valid, hist);
   }
   __syncthreads();
-  if (t < kBuckets) counts[(int64_t)blockIdx.x * kBuckets + t] = hist[t];
+  if (t < kBuckets) counts[blk * kBuckets + t] = hist[t];
+}
+
+__global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
+    const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
+    int R, const float* __restrict__ far, const uint8_t* __restrict__ forced,
+    int mode, int L, int max_depth, uint8_t* __restrict__ depth,
+    float* __restrict__ sdf, float* __restrict__ grad, int32_t* __restrict__ counts) {
+  lookup_block(blockIdx.x, xyz, n, map, R, far, forced, mode, L, max_depth, depth, sdf, grad,
+               counts);
 }
 
 constexpr int kScanThreads = 256;
@@ -109,9 +121,8 @@ constexpr int kScanThreads = 256;
 // One workgroup: per-chunk histograms -> per-chunk bucket offsets (in
 // place) and the tile plan. Bucket d >= 1 occupies perm slots
 // [start[d], start[d] + count[d]); depth-0 points are not in the permutation.
-__global__ __launch_bounds__(kScanThreads) void k_scan(int32_t* __restrict__ counts,
-                                                      int64_t nblk, int L, int tile_q,
-                                                      Plan* __restrict__ plan) {
+__device__ __forceinline__ void scan_body(int32_t* __restrict__ counts, int64_t nblk, int L,
+                                          int tile_q, Plan* __restrict__ plan) {
   __shared__ int64_t part[kScanThreads][kBuckets];
   __shared__ int64_t start[kBuckets];
   const int t = threadIdx.x;
@@ -167,14 +178,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int32_t* __restrict__ cou
     }
 }
 
-__global__ __launch_bounds__(kLookupThreads) void k_scatter(
-    const uint8_t* __restrict__ depth, int64_t n, const int32_t* __restrict__ offs,
-    int32_t* __restrict__ perm) {
+__global__ __launch_bounds__(kScanThreads) void k_scan(int32_t* __restrict__ counts,
+                                                      int64_t nblk, int L, int tile_q,
+                                                      Plan* __restrict__ plan) {
+  scan_body(counts, nblk, L, tile_q, plan);
+}
+
+__device__ __forceinline__ void scatter_block(int64_t blk, const uint8_t* __restrict__ depth,
+                                              int64_t n, const int32_t* __restrict__ offs,
+                                              int32_t* __restrict__ perm) {
   __shared__ int run[kBuckets];
   __shared__ int wcnt[kLookupThreads / 64][kBuckets];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t base = (int64_t)blockIdx.x * kLookupChunk;
-  if (t < kBuckets) run[t] = offs[(int64_t)blockIdx.x * kBuckets + t];
+  const int64_t base = blk * kLookupChunk;
+  if (t < kBuckets) run[t] = offs[blk * kBuckets + t];
   for (int r = 0; r < kRounds; ++r) {
     const int64_t q0 = base + (int64_t)r * kLookupThreads;
     if (q0 >= n) break;
@@ -210,6 +227,57 @@ __global__ __launch_bounds__(kLookupThreads) void k_scatter(
   }
 }
 
+__global__ __launch_bounds__(kLookupThreads) void k_scatter(
+    const uint8_t* __restrict__ depth, int64_t n, const int32_t* __restrict__ offs,
+    int32_t* __restrict__ perm) {
+  scatter_block(blockIdx.x, depth, n, offs, perm);
+}
+
+// ---- batched variants: one launch covers several queries (server) ----
+
+// Request owning lookup block b: the last r with reqs[r].blk0 <= b.
+__device__ __forceinline__ int find_request(const BatchReq* reqs, int nreq, int64_t b) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (reqs[mid].blk0 <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kLookupThreads) void k_lookup_batch(const BatchReq* __restrict__ reqs,
+                                                                 int nreq, int max_depth) {
+  const int r = find_request(reqs, nreq, blockIdx.x);
+  const BatchReq& q = reqs[r];
+  lookup_block((int64_t)blockIdx.x - q.blk0, q.xyz, q.n, q.map, q.R, q.far, nullptr, 0, q.L,
+               max_depth, q.depth, q.sdf, nullptr, q.counts);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_batch(BatchReq* __restrict__ reqs,
+                                                            int tile_q) {
+  BatchReq& q = reqs[blockIdx.x];
+  scan_body(q.counts, (q.n + kLookupChunk - 1) / kLookupChunk, q.L, tile_q, &q.plan);
+}
+
+__global__ __launch_bounds__(kLookupThreads) void k_scatter_batch(const BatchReq* __restrict__ reqs,
+                                                                  int nreq) {
+  const int r = find_request(reqs, nreq, blockIdx.x);
+  const BatchReq& q = reqs[r];
+  scatter_block((int64_t)blockIdx.x - q.blk0, q.depth, q.n, q.counts, q.perm);
+}
+
+// First tile of every request and the batch's tile count.
+__global__ void k_batch_tiles(BatchReq* __restrict__ reqs, int nreq,
+                              int64_t* __restrict__ total) {
+  if (threadIdx.x != 0) return;
+  int64_t run = 0;
+  for (int r = 0; r < nreq; ++r) {
+    reqs[r].tile0 = run;
+    run += reqs[r].plan.total_tiles;
+  }
+  *total = run;
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -240,6 +308,16 @@ hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
   const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, depth, n,
                      offs, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_bucketing_batch(BatchReq* reqs, int nreq, int64_t nblk, int max_depth,
+                                  int tile_q, int64_t* total_tiles, hipStream_t s) {
+  hipLaunchKernelGGL(k_lookup_batch, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, reqs, nreq,
+                     max_depth);
+  hipLaunchKernelGGL(k_scan_batch, dim3((unsigned)nreq), dim3(kScanThreads), 0, s, reqs, tile_q);
+  hipLaunchKernelGGL(k_scatter_batch, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, reqs, nreq);
+  hipLaunchKernelGGL(k_batch_tiles, dim3(1), dim3(64), 0, s, reqs, nreq, total_tiles);
   return hipGetLastError();
 }
 

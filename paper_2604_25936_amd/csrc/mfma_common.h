@@ -156,6 +156,16 @@ struct Cfg {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// LDS pointer of a generic pointer into a __shared__ array: the low 32 bits
+// of a flat address in the LDS aperture are the LDS offset. (A plain cast
+// inserts a null check that the gfx950 backend can fail to select.)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wint-to-void-pointer-cast"
+__device__ __forceinline__ lds_void* lds_ptr(const void* p) {
+  return (lds_void*)(uint32_t)(uintptr_t)p;
+}
+#pragma clang diagnostic pop
+
 // Start copying one chunk of BYTES bytes from global memory into an LDS slot
 // without passing through registers: each wavefront-wide load moves 64
 // pieces of 16 bytes to 1 KB of LDS. Completion is awaited (vmcnt) before the
@@ -170,8 +180,8 @@ __device__ __forceinline__ void load_chunk(const char* __restrict__ src, char* d
     const int q = k * NW + wave;
     const int piece = q * 64 + lane;
     if (q * 64 < NP && piece < NP)
-      __builtin_amdgcn_global_load_lds((const void*)(src + piece * 16), (lds_void*)(dst + q * 1024),
-                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(src + piece * 16), lds_ptr(dst + q * 1024), 16,
+                                       0, 0);
   }
 }
 

@@ -16,12 +16,15 @@ struct sand_model_s {
   // input-gradient data (same allocation): transposed chunks per precision,
   // omega_1 W_1 rows and the tail table
   const char* bwd[3] = {nullptr, nullptr, nullptr};
+  // device copies of args[] (read per tile by batched launches)
+  const sand::ModelArgs* args_dev[3] = {nullptr, nullptr, nullptr};
   const float* w1t = nullptr;
   const float* tails = nullptr;
 };
 
 struct sand_depthmap_s {
-  sand_model model = nullptr;
+  sand_model model = nullptr;   // identity only: never dereferenced when freeing
+  int device = 0;               // so the map can be freed after its model
   int R = 0;
   uint8_t* depth = nullptr;   // device [R^3]
   float* far = nullptr;       // device [R^3] or null

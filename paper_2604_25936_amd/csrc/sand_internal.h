@@ -81,6 +81,32 @@ struct QueryArgs {
   int full_depth;          // FULL mode: the depth every point runs to
 };
 
+// One query of a batched launch (server). Pointers are device memory; the
+// lookup/scan kernels fill plan and tile0.
+struct BatchReq {
+  const float* xyz;        // [n][3]
+  float* sdf;              // [n]
+  uint8_t* depth;          // [n] scratch
+  int32_t* perm;           // [n] scratch
+  int32_t* counts;         // [ceil(n/4096)][kBuckets] scratch
+  const uint8_t* map;      // R^3 depth map
+  const float* far;        // R^3 far values or null
+  const ModelArgs* model;  // device copy of the model's arguments
+  int64_t n;
+  int64_t blk0;            // first lookup block of this query in the launch
+  int64_t tile0;           // first T-MLP tile of this query (device-filled)
+  int R;
+  int L;
+  Plan plan;               // device-filled
+};
+
+// Everything one batched T-MLP launch needs.
+struct BatchArgs {
+  const BatchReq* reqs;
+  int nreq;
+  const int64_t* total_tiles;   // device-filled by the bucketing launch
+};
+
 // Everything one input-gradient launch needs.
 struct AdjointArgs {
   QueryArgs q;             // forward chunks, points, optional sdf out, plan
@@ -103,6 +129,9 @@ hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q,
 hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
                           int32_t* perm, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_bucketing_batch(BatchReq* reqs, int nreq, int64_t nblk, int max_depth,
+                                  int tile_q, int64_t* total_tiles, hipStream_t s);
+hipError_t launch_tmlp_batch(int prec, int WP, const BatchArgs& a, int num_cu, hipStream_t s);
 
 int tmlp_tile_points(int prec);
 size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L);

@@ -121,86 +121,141 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
   return add_tail<PREC>(y, s0, s1, c0, c1);
 }
 
+// Decode tile `tile` of a plan: exit depth, first permutation slot, count.
+template <int Q>
+__device__ __forceinline__ void decode_tile(const Plan* plan, int L, int64_t tile, int& d,
+                                            int64_t& start, int64_t& cnt) {
+  d = 1;
+  for (int dd = L; dd >= 1; --dd)
+    if (tile < plan->tile_end[dd]) {
+      d = dd;
+      break;
+    }
+  const int64_t local = tile - plan->tile_end[d + 1];
+  start = plan->start[d] + local * Q;
+  cnt = plan->count[d] - local * Q;
+  if (cnt > Q) cnt = Q;
+}
+
+// Evaluate one tile: cnt points of exit depth d, the i-th being point
+// perm[start + i] (or start + i without a permutation).
 template <int PREC, int WP>
-__global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
+__device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __restrict__ xyz,
+                                         float* __restrict__ sdf, const int32_t* __restrict__ perm,
+                                         int64_t start, int64_t cnt, int d, char* ring,
+                                         const char* l1, int lane, int wave) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
+  const int g = T::grp(lane), col = T::col(lane);
+  const char* hidden = M.chunks + C::L1B;
+
+  // This wavefront's point; every lane of the same column holds it.
+  const int qi = wave * T::NQ + col;
+  const bool ok = qi < cnt;
+  int64_t gi = 0;
+  float px = 0.0f, py = 0.0f, pz = 0.0f;
+  if (ok) {
+    gi = perm ? (int64_t)perm[start + qi] : start + qi;
+    const float* p = xyz + 3 * gi;
+    px = p[0];
+    py = p[1];
+    pz = p[2];
+  }
+
+  V actA[C::KS], actB[C::KS];
+  float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+  for (int rb = 0; rb < C::RB; ++rb) {
+    const char* ch = l1 + rb * C::L1C;
+    typename T::Acc acc = {};
+#pragma unroll
+    for (int st = 0; st < T::L1S; ++st)
+      acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
+    epilogue<PREC, C::KS>(ch + T::L1S * 256, g, rb, acc, actA, s0, s1);
+    pin_block<PREC, C::KS>(actA, rb, s0, s1);
+  }
+  float y = add_tail<PREC>(0.0f, s0, s1, M.c0[0], M.c1[0]);
+
+  const int nc = (d - 1) * C::RB;
+  int c = 0;
+  if (nc > 0) {
+    load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
+    wait_chunk();
+    __syncthreads();
+  }
+  for (int j = 2; j <= d; j += 2) {
+    y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actA, actB, M.c0[j - 1],
+                               M.c1[j - 1]);
+    if (j + 1 > d) break;
+    y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, M.c0[j],
+                               M.c1[j]);
+  }
+  if (g == 0 && ok) sdf[gi] = y;
+}
+
+template <int PREC, int WP>
+__device__ __forceinline__ void load_layer1(const ModelArgs& M, char* l1, int tid) {
+  using C = Cfg<PREC, WP>;
+  for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)M.chunks)[i];
+}
+
+template <int PREC, int WP>
+__global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
+  using C = Cfg<PREC, WP>;
   constexpr int Q = C::Q;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
   char* ring = lds;
   char* l1 = lds + 2 * C::CH;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = T::grp(lane), col = T::col(lane);
-
-  for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)a.m.chunks)[i];
+  load_layer1<PREC, WP>(a.m, l1, tid);
   __syncthreads();
-  const char* hidden = a.m.chunks + C::L1B;
-  const int L = a.m.L;
   const int64_t total = a.plan ? a.plan->total_tiles : (a.n + Q - 1) / Q;
-
   for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
     int d;
     int64_t start, cnt;
     if (a.plan) {
-      d = 1;
-      for (int dd = L; dd >= 1; --dd)
-        if (tile < a.plan->tile_end[dd]) {
-          d = dd;
-          break;
-        }
-      const int64_t local = tile - a.plan->tile_end[d + 1];
-      start = a.plan->start[d] + local * Q;
-      cnt = a.plan->count[d] - local * Q;
+      decode_tile<Q>(a.plan, a.m.L, tile, d, start, cnt);
     } else {
       d = a.full_depth;
       start = tile * Q;
-      cnt = a.n - start;
+      cnt = a.n - start < Q ? a.n - start : Q;
     }
-    if (cnt > Q) cnt = Q;
+    run_tile<PREC, WP>(a.m, a.xyz, a.sdf, a.perm, start, cnt, d, ring, l1, lane, wave);
+  }
+}
 
-    // This wavefront's point; every lane of the same column holds it.
-    const int qi = wave * T::NQ + col;
-    const bool ok = qi < cnt;
-    int64_t gi = 0;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
-    if (ok) {
-      gi = a.perm ? (int64_t)a.perm[start + qi] : start + qi;
-      const float* p = a.xyz + 3 * gi;
-      px = p[0];
-      py = p[1];
-      pz = p[2];
+// Several queries (possibly of different models of the same padded width)
+// in one persistent launch: tile t belongs to the last query whose first
+// tile is <= t. Layer-1 weights are reloaded into LDS when the model changes.
+template <int PREC, int WP>
+__global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp_batch(BatchArgs a) {
+  using C = Cfg<PREC, WP>;
+  constexpr int Q = C::Q;
+  __shared__ __attribute__((aligned(16))) char ring[2 * C::CH];
+  __shared__ __attribute__((aligned(16))) char l1[C::L1B];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t cur = 0;   // address of the model whose layer 1 is in LDS
+  const int64_t total = *a.total_tiles;
+  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    int lo = 0, hi = a.nreq - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.reqs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
     }
-
-    V actA[C::KS], actB[C::KS];
-    float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll
-    for (int rb = 0; rb < C::RB; ++rb) {
-      const char* ch = l1 + rb * C::L1C;
-      typename T::Acc acc = {};
-#pragma unroll
-      for (int st = 0; st < T::L1S; ++st)
-        acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
-      epilogue<PREC, C::KS>(ch + T::L1S * 256, g, rb, acc, actA, s0, s1);
-      pin_block<PREC, C::KS>(actA, rb, s0, s1);
-    }
-    float y = add_tail<PREC>(0.0f, s0, s1, a.m.c0[0], a.m.c1[0]);
-
-    const int nc = (d - 1) * C::RB;
-    int c = 0;
-    if (nc > 0) {
-      load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
-      wait_chunk();
+    const BatchReq& q = a.reqs[lo];
+    const ModelArgs& M = *q.model;
+    const uint64_t key = (uint64_t)(uintptr_t)q.model;
+    if (key != cur) {
+      __syncthreads();   // every wavefront is done with the previous layer-1 copy
+      load_layer1<PREC, WP>(M, l1, tid);
       __syncthreads();
+      cur = key;
     }
-    for (int j = 2; j <= d; j += 2) {
-      y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actA, actB, a.m.c0[j - 1],
-                                 a.m.c1[j - 1]);
-      if (j + 1 > d) break;
-      y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, a.m.c0[j],
-                                 a.m.c1[j]);
-    }
-    if (g == 0 && ok) a.sdf[gi] = y;
+    int d;
+    int64_t start, cnt;
+    decode_tile<Q>(&q.plan, q.L, tile - q.tile0, d, start, cnt);
+    run_tile<PREC, WP>(M, q.xyz, q.sdf, q.perm, start, cnt, d, ring, l1, lane, wave);
   }
 }
 
@@ -228,9 +283,33 @@ hipError_t launch_prec(const QueryArgs& a, int num_cu, hipStream_t s) {
   }
 }
 
+template <int PREC, int WP>
+hipError_t launch_batch_one(const BatchArgs& a, int num_cu, hipStream_t s) {
+  hipLaunchKernelGGL((k_tmlp_batch<PREC, WP>), dim3((unsigned)num_cu), dim3(Cfg<PREC, WP>::NT), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_batch_prec(int WP, const BatchArgs& a, int num_cu, hipStream_t s) {
+  switch (WP) {
+    case 64: return launch_batch_one<PREC, 64>(a, num_cu, s);
+    case 128: return launch_batch_one<PREC, 128>(a, num_cu, s);
+    case 256: return launch_batch_one<PREC, 256>(a, num_cu, s);
+    case 352: return launch_batch_one<PREC, 352>(a, num_cu, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 int tmlp_tile_points(int prec) { return 8 * (prec == PREC_FP32 ? 16 : 32); }
+
+hipError_t launch_tmlp_batch(int prec, int WP, const BatchArgs& a, int num_cu, hipStream_t s) {
+  if (prec == PREC_FP32) return launch_batch_prec<PREC_FP32>(WP, a, num_cu, s);
+  if (prec == PREC_BF16) return launch_batch_prec<PREC_BF16>(WP, a, num_cu, s);
+  return launch_batch_prec<PREC_FP16>(WP, a, num_cu, s);
+}
 
 hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s) {
   if (prec == PREC_FP32) return launch_prec<PREC_FP32>(a, num_cu, s);

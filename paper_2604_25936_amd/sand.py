@@ -32,6 +32,13 @@ class QueryOpts(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_size_t), ("reserved_bytes", ctypes.c_size_t),
+                ("peak_reserved_bytes", ctypes.c_size_t), ("submitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("max_batch_requests", ctypes.c_int32), ("in_flight_batches", ctypes.c_int32)]
+
+
 class ReqStats(ctypes.Structure):
     _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double),
@@ -67,6 +74,7 @@ def library():
             "sand_server_create": (I32, [ctypes.c_int, SZ, I32, I32, ctypes.POINTER(P)]),
             "sand_server_submit": (I32, [P, P, P, P, I64, P, ctypes.POINTER(U64)]),
             "sand_server_wait": (I32, [P, U64, ctypes.c_double, ctypes.POINTER(ReqStats)]),
+            "sand_server_stats": (I32, [P, ctypes.POINTER(ServerInfo)]),
             "sand_server_destroy": (None, [P]),
             "sand_status_str": (ctypes.c_char_p, [I32]),
             "sand_last_error": (ctypes.c_char_p, []),
@@ -243,3 +251,70 @@ def query_grad(model, dmap, xyz, dy=None, sdf_out=None, grad_out=None, precision
                                      n, _ptr(dy), _ptr(sdf_out), _ptr(grad_out), ctypes.byref(o),
                                      _stream(stream)))
     return grad_out
+
+
+class Server:
+    """The request loop of one GPU (sand_server_*).
+
+    submit() takes host arrays (numpy float32 [n, 3] points and a float32 [n]
+    result buffer, ideally pinned) and returns a ticket; wait() blocks until
+    that request's results are in its buffer and returns its time stamps.
+    The arrays must stay alive until wait() returns for their ticket.
+    """
+
+    def __init__(self, device=0, budget_bytes=4 << 30, precision="bf16", n_streams=2):
+        h = ctypes.c_void_p()
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(library().sand_server_create(device, int(budget_bytes), p, int(n_streams),
+                                            ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, model, dmap, xyz, sdf_out):
+        t = ctypes.c_uint64()
+        xp = _host_ptr(xyz, np.float32, 2)
+        yp = _host_ptr(sdf_out, np.float32, 1)
+        n = int(xyz.shape[0])
+        if sdf_out.shape[0] != n:
+            raise ValueError("result buffer has the wrong length")
+        _check(library().sand_server_submit(self._h, model.handle, dmap.handle, xp, n, yp,
+                                            ctypes.byref(t)))
+        self._keep[t.value] = (xyz, sdf_out, model, dmap)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        st = ReqStats()
+        try:
+            _check(library().sand_server_wait(self._h, ticket, float(timeout), ctypes.byref(st)))
+        except SandError as e:
+            if e.status != ERR_TIMEOUT:
+                self._keep.pop(ticket, None)
+            raise
+        self._keep.pop(ticket, None)
+        return {k: getattr(st, k) for k, _ in ReqStats._fields_}
+
+    def stats(self):
+        info = ServerInfo()
+        _check(library().sand_server_stats(self._h, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.sand_server_destroy(self._h)
+        self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        self.close()
+
+
+def _host_ptr(a, dtype, ndim):
+    """Data pointer of a host array (numpy, or a CPU torch tensor)."""
+    if hasattr(a, "data_ptr"):
+        if a.is_cuda or not a.is_contiguous():
+            raise ValueError("server buffers must be contiguous host tensors")
+        return ctypes.c_void_p(a.data_ptr())
+    if not isinstance(a, np.ndarray) or a.dtype != dtype or a.ndim != ndim or \
+            not a.flags.c_contiguous:
+        raise ValueError("server buffers must be C-contiguous float32 numpy arrays")
+    return a.ctypes.data_as(ctypes.c_void_p)

@@ -112,3 +112,17 @@ def test_python_binding_argument_checks():
         sand._check_points(torch.zeros(3, 5).t())
     with pytest.raises(KeyError):
         sand._opts("fp64", "adaptive", 0, None, None, None)
+
+
+def test_server_argument_errors():
+    lib = sand.library()
+    h = ctypes.c_void_p()
+    assert lib.sand_server_create(0, 1 << 30, 7, 2, ctypes.byref(h)) == sand.ERR_INVALID
+    assert lib.sand_server_create(0, 1 << 30, 1, 0, ctypes.byref(h)) == sand.ERR_INVALID
+    assert lib.sand_server_create(0, 1000, 1, 2, ctypes.byref(h)) == sand.ERR_INVALID
+    assert lib.sand_server_create(0, 1 << 30, 1, 2, None) == sand.ERR_INVALID
+    t = ctypes.c_uint64()
+    assert lib.sand_server_submit(None, None, None, None, 0, None, ctypes.byref(t)) == sand.ERR_INVALID
+    assert lib.sand_server_wait(None, 1, 0.0, None) == sand.ERR_INVALID
+    assert lib.sand_server_stats(None, None) == sand.ERR_INVALID
+    lib.sand_server_destroy(None)

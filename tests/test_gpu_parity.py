@@ -257,3 +257,16 @@ def test_512_grid_bench_configuration():
     got = sdf[torch.from_numpy(idx[:4000]).to(DEV)].cpu().numpy().astype(np.float64)
     assert_close(got, oracle.forward(ref, xs[:4000], np.full(4000, 8)), TOL["fp32"],
                  "512^3 fp32 full sample")
+
+
+def test_free_model_before_map():
+    """A map may be freed after its model (finalizers of unreachable objects
+    run in any order); nothing may leave a device error behind."""
+    blob = synth.write_blob(synth.siren_tmlp(3, 2, 32))
+    model = sand.load_model(blob, 0)
+    dm = sand.build_depthmap(model, np.ones((4, 4, 4), dtype=np.uint8))
+    model.free()
+    dm.free()
+    t = torch.full((1000,), 7, dtype=torch.uint8, device=DEV)
+    torch.cuda.synchronize()
+    assert int(t.sum().item()) == 7000
