@@ -97,13 +97,185 @@ def cpu_baseline(blob, dmap, n_sample, target_s=12.0):
                       f"map, FP64 numpy (lookup + adaptive forward), {dt:.1f} s"}
 
 
+def _c4_inputs(k):
+    """Map and near-surface point pool of serving model k (CPU, generator only)."""
+    import synth
+    prims = synth.random_primitives(SURFACE_SEED + k)
+    dmap = synth.band_map_c2(prims, R=128, L=L)
+    pool = synth.near_surface_points(prims, 1 << 15, seed=5000 + k)
+    return dmap, pool
+
+
+def _c5_points():
+    import synth
+    return synth.camera_ray_points(synth.random_primitives(SURFACE_SEED), 77)
+
+
+def gen_inputs(legs, n_models):
+    """All CPU-side inputs, generated in worker processes before the GPU is used."""
+    import concurrent.futures
+    import synth
+    out = {}
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers) as ex:
+        fut_c2 = ex.submit(synth.band_map_c2, synth.random_primitives(SURFACE_SEED), 128, L)
+        fut_c5 = ex.submit(_c5_points) if "grad" in legs else None
+        fut_c4 = [ex.submit(_c4_inputs, k) for k in range(n_models)] if "serving" in legs else []
+        out["c2_map"] = fut_c2.result()
+        if fut_c5 is not None:
+            out["c5_points"] = fut_c5.result()
+        out["c4"] = [f.result() for f in fut_c4]
+    return out
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+def serving_leg(sand, torch, inputs, n_models, n_payloads=128, n_measure=2000):
+    """Poisson request stream over n_models resident 8x256 models (BF16)."""
+    import numpy as np
+    import synth
+    rng = np.random.Generator(np.random.PCG64(7))
+    models, maps = [], []
+    for k in range(n_models):
+        blob = synth.write_blob(synth.siren_tmlp(MODEL_SEED + k, L, W, tails="mult",
+                                                 scale="residual"))
+        m = sand.load_model(blob, 0)
+        models.append(m)
+        maps.append(sand.build_depthmap(m, inputs["c4"][k][0]))
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(4e6), size=n_payloads)).astype(np.int64)
+    payloads = []
+    for i, n in enumerate(sizes):
+        k = i % n_models
+        half = int(n) // 2
+        start = int(rng.integers(0, G ** 3 - half))
+        slab = synth.grid_points_at(G, np.arange(start, start + half, dtype=np.int64))
+        pool = inputs["c4"][k][1]
+        near = pool[rng.integers(0, len(pool), size=int(n) - half)]
+        x = torch.from_numpy(np.concatenate([slab, near])).pin_memory()
+        y = torch.empty(int(n), dtype=torch.float32).pin_memory()
+        payloads.append((k, x, y))
+    budget = 4 << 30
+    srv = sand.Server(0, budget_bytes=budget, precision="bf16", n_streams=3)
+
+    def run(order, gaps):
+        tickets = []
+        t0 = time.perf_counter()
+        t_next = t0
+        for j, i in enumerate(order):
+            if gaps is not None:
+                t_next += gaps[j]
+                while time.perf_counter() < t_next:
+                    pass
+            k, x, y = payloads[i]
+            tickets.append((srv.submit(models[k], maps[k], x, y), x.shape[0]))
+        st = [srv.wait(t) for t, _ in tickets]
+        lat = [s["t_copied"] - s["t_submit"] for s in st]
+        pts = sum(n for _, n in tickets)
+        span = max(s["t_copied"] for s in st) - min(s["t_submit"] for s in st)
+        return lat, pts, span, st
+
+    run(list(range(16)), None)                       # warm-up
+    lat, pts, span, _ = run(list(range(n_payloads)), None)   # burst: saturated rate
+    sat_qps, sat_rps = pts / span, n_payloads / span
+    mean_pts = float(sizes.mean())
+    out = {"models": n_models, "payloads": n_payloads, "mean_request_points": mean_pts,
+           "hbm_budget_bytes": budget, "streams": 3, "saturated_queries_per_s": sat_qps,
+           "saturated_requests_per_s": sat_rps, "loads": {}}
+    for load in (0.5, 0.8):
+        rate = load * sat_rps
+        gaps = rng.exponential(1.0 / rate, size=n_measure)
+        order = [int(i) for i in rng.integers(0, n_payloads, size=n_measure)]
+        log(f"serving: Poisson {rate:.0f} requests/s ({load}x saturation), {n_measure} requests")
+        lat, pts, span, st = run(order, gaps)
+        out["loads"][str(load)] = {
+            "offered_requests_per_s": rate, "queries_per_s": pts / span,
+            "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+            "mean_batch_requests": float(np.mean([s["batch_size"] for s in st])),
+        }
+    info = srv.stats()
+    out["peak_reserved_bytes"] = info["peak_reserved_bytes"]
+    out["batches"] = info["batches"]
+    srv.close()
+    return out
+
+
+def grad_leg(sand, torch, inputs, dm_model):
+    """Forward + input gradient over 1920x1080 camera-ray samples (8x256)."""
+    import numpy as np
+    import oracle
+    model, dm, blob, dmap = dm_model
+    x = inputs["c5_points"]
+    xyz = torch.from_numpy(x).to("cuda:0")
+    n = xyz.shape[0]
+    sdf = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    g = torch.empty((n, 3), dtype=torch.float32, device="cuda:0")
+    out = {"points": n}
+    for prec in ("bf16", "fp32"):
+        ws = torch.empty(sand.query_grad_workspace_size(model, n, prec), dtype=torch.uint8,
+                         device="cuda:0")
+        t = time_steps(lambda: sand.query_grad(model, dm, xyz, sdf_out=sdf, grad_out=g,
+                                               precision=prec, workspace=ws), 5, 2)
+        idx = np.random.Generator(np.random.PCG64(3)).choice(n, 4000, replace=False)
+        ref = oracle.parse_blob(blob)
+        d = oracle.lookup_depth(x[idx], dmap, L)
+        want = oracle.gradient(ref, x[idx], d)
+        got = g.cpu().numpy()[idx].astype(np.float64)
+        rel = np.linalg.norm(got - want, axis=1) / np.maximum(np.linalg.norm(want, axis=1), 1e-12)
+        out[prec] = {"queries_per_s": n / t, "ms_per_step": t * 1e3,
+                     "grad_max_rel_err_4k_sample": float(rel.max()),
+                     "grad_mean_rel_err_4k_sample": float(rel.mean())}
+    return out
+
+
+def c3_leg(sand, torch, xyz, dmap, n_err=1 << 20):
+    """8x336 on the 512^3 grid: throughput per precision and the error study
+    (max/mean |SDF error| vs the FP64 oracle on a seeded 1M-point sample, and
+    sign agreement among sample points with |y_oracle| < 0.01)."""
+    import numpy as np
+    import oracle
+    import synth
+    blob = synth.write_blob(synth.siren_tmlp(MODEL_SEED + 336, L, 336, tails="mult",
+                                             scale="residual"))
+    model = sand.load_model(blob, 0)
+    dm = sand.build_depthmap(model, dmap)
+    n = xyz.shape[0]
+    sdf = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    ws = torch.empty(sand.query_workspace_size(n), dtype=torch.uint8, device="cuda:0")
+    idx = synth.sample_indices(n, n_err, seed=11)
+    xs = synth.grid_points_at(G, idx)
+    ref = oracle.parse_blob(blob)
+    want = oracle.forward(ref, xs, oracle.lookup_depth(xs, dmap, L))
+    near = np.abs(want) < 0.01
+    idx_t = torch.from_numpy(idx).to("cuda:0")
+    out = {"sample_points": n_err, "sample_points_near_surface": int(near.sum())}
+    for prec, mode in (("bf16", "adaptive"), ("fp16", "adaptive"), ("fp32", "adaptive"),
+                       ("fp32", "full")):
+        k = 2 if mode == "full" else 3
+        t = time_steps(lambda: sand.query(model, dm, xyz, out=sdf, precision=prec, mode=mode,
+                                          workspace=ws), k, 1)
+        r = {"queries_per_s": n / t, "ms_per_step": t * 1e3}
+        if mode == "adaptive":
+            got = sdf[idx_t].cpu().numpy().astype(np.float64)
+            err = np.abs(got - want)
+            r.update({"max_abs_err": float(err.max()), "mean_abs_err": float(err.mean()),
+                      "sign_agreement_near_surface": float(np.mean(
+                          np.sign(got[near]) == np.sign(want[near]))) if near.any() else None})
+        out[f"{mode}_{prec}"] = r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--legs", default="all", help="'all' or 'headline' (profiling runs)")
+    ap.add_argument("--legs", default="all",
+                    help="'all', or a comma list of headline,compare,c3,grad,serving,cpu")
     ap.add_argument("--cpu-sample", type=int, default=131072)
+    ap.add_argument("--serving-models", type=int, default=64)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
@@ -112,6 +284,11 @@ def main():
               "shards by splitting the point set, with no exchange, and is not run on several "
               "GPUs here.", file=sys.stderr)
         sys.exit(2)
+    legs = {"headline", "compare", "c3", "grad", "serving", "cpu"} if args.legs == "all" else \
+        set(args.legs.split(",")) | {"headline"}
+
+    log("generating inputs on the host")
+    inputs = gen_inputs(legs, args.serving_models)
 
     import numpy as np
     import torch
@@ -121,7 +298,7 @@ def main():
     dev = "cuda:0"
     log("building inputs: 8x256 T-MLP, 128^3 map, 512^3 grid")
     blob = synth.write_blob(synth.siren_tmlp(MODEL_SEED, L, W, tails="mult", scale="residual"))
-    dmap = synth.band_map_c2(synth.random_primitives(SURFACE_SEED), R=128, L=L)
+    dmap = inputs["c2_map"]
     model = sand.load_model(blob, 0)
     dm = sand.build_depthmap(model, dmap)
     xyz = synth.queries.grid_points_torch(G, dev)
@@ -163,10 +340,9 @@ def main():
                 "traffic": measured_traffic()}
 
     comparisons = {}
-    if args.legs == "all":
-        legs = [("fp32", "full"), ("fp32", "adaptive"), ("bf16", "full"), ("fp16", "adaptive"),
-                ("fp16", "full")]
-        for prec, mode in legs:
+    if "compare" in legs:
+        for prec, mode in [("fp32", "full"), ("fp32", "adaptive"), ("bf16", "full"),
+                           ("fp16", "adaptive"), ("fp16", "full")]:
             k = 2 if (prec == "fp32" and mode == "full") else 3
             log(f"comparison: {mode} {prec}, {k} steps")
             t = time_steps(step(prec, mode), k, 1)
@@ -197,7 +373,25 @@ def main():
         "hidden_mfma_flop_per_step": flops,
         "comparisons": comparisons,
     }
-    if args.cpu_sample > 0 and args.legs == "all":
+    def secondary(name, fn):
+        # a failing secondary leg is reported in its entry; the headline stands
+        try:
+            line[name] = fn()
+        except Exception as e:  # noqa: BLE001
+            log(f"{name} leg failed: {e!r}")
+            line[name] = {"error": repr(e)}
+
+    if "c3" in legs:
+        log("8x336 leg: throughput per precision and error study")
+        secondary("width336", lambda: c3_leg(sand, torch, xyz, dmap))
+    del ws
+    if "grad" in legs:
+        log("gradient leg: 1920x1080 camera-ray samples")
+        secondary("gradient", lambda: grad_leg(sand, torch, inputs, (model, dm, blob, dmap)))
+    if "serving" in legs:
+        log(f"serving leg: {args.serving_models} resident models")
+        secondary("serving", lambda: serving_leg(sand, torch, inputs, args.serving_models))
+    if args.cpu_sample > 0 and "cpu" in legs:
         log(f"cpu baseline: oracle on {args.cpu_sample} sampled points")
         line["cpu_baseline"] = cpu_baseline(blob, dmap, args.cpu_sample)
     print(json.dumps(line), flush=True)

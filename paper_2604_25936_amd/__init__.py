@@ -7,7 +7,9 @@ This package is the Python binding of that library.
 """
 
 from .sand import (Model, DepthMap, Server, SandError, load_model, build_depthmap, query,
-                   query_timed, query_grad, query_workspace_size, library, PRECISIONS, MODES)
+                   query_timed, query_grad, query_workspace_size,
+                   query_grad_workspace_size, library, PRECISIONS, MODES)
 
 __all__ = ["Model", "DepthMap", "Server", "SandError", "load_model", "build_depthmap", "query",
-           "query_timed", "query_grad", "query_workspace_size", "library", "PRECISIONS", "MODES"]
+           "query_timed", "query_grad", "query_workspace_size",
+           "query_grad_workspace_size", "library", "PRECISIONS", "MODES"]
