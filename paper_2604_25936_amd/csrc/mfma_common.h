@@ -149,7 +149,8 @@ struct Cfg {
   static constexpr int CH_B = TAIL_OFF_B + T::BM * 8;
   static constexpr int L1C = T::L1S * 256 + T::BM * 8;   // layer-1 chunk bytes
   static constexpr int L1B = RB * L1C;
-  static constexpr int LDS = 2 * CH + L1B;
+  static constexpr int NSLOT = 3;                        // forward LDS ring slots
+  static constexpr int LDS = NSLOT * CH + L1B;
   static_assert(CH % 16 == 0 && CH_B % 16 == 0 && L1B % 16 == 0,
                 "chunks are whole 16-byte pieces");
 };

@@ -21,9 +21,11 @@
 //  * Epilogue per element: hardware sine in revolutions (weights carry
 //    omega/(2 pi)), two FP32 FMAs for the two tail factors, pack. The lanes
 //    holding disjoint units of one point are summed by cross-lane exchange.
-//  * Weights stream through a two-slot LDS ring, one output block
+//  * Weights stream through a three-slot LDS ring, one output block
 //    ("chunk") at a time: direct global-to-LDS loads of chunk c+1 are in
 //    flight while chunk c feeds the MFMAs.
+//  * Software pipelining: each wavefront issues the MFMAs of block rb
+//    together with the sine/tail epilogue of block rb-1.
 //  * Eight wavefronts per workgroup, two per SIMD: while one wavefront runs
 //    its sine/tail epilogue on the vector ALU the other keeps the matrix
 //    core busy.
@@ -85,8 +87,29 @@ __device__ __forceinline__ float add_tail(float y, float s0, float s1, float c0,
   return fmaf(T::lane_sum(s0) + c0, T::lane_sum(s1) + c1, y);
 }
 
-// One hidden layer: in -> out, streaming its RB chunks through the LDS ring.
-// c is the tile's running chunk index, nc its chunk count.
+// MFMA chain of one output block: bias + W_j h over all K steps, A operands
+// from the LDS slot holding the block's chunk.
+template <int PREC, int WP>
+__device__ __forceinline__ typename Tr<PREC>::Acc block_mma(
+    const char* slot, int lane, const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
+    const typename Tr<PREC>::V& bb) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  typename T::Acc acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb,
+                               typename T::Acc{});
+#pragma unroll
+  for (int s = 0; s < C::KS; ++s) acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
+  return acc;
+}
+
+// One hidden layer: in -> out, streaming its RB chunks through a three-slot
+// LDS ring. Software-pipelined: the MFMAs of block rb are issued together
+// with the (independent) sine/tail epilogue of block rb-1, so one
+// wavefront keeps the matrix core and the vector ALU busy at once. Chunk c
+// lives in slot c % 3; while block rb (chunk c) feeds the MFMAs and block
+// rb-1's tail weights (chunk c-1) feed the epilogue, chunk c+1 streams into
+// the third slot. c is the tile's running chunk index, nc its chunk count.
 template <int PREC, int WP>
 __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ hidden, char* ring,
                                               int wave, int lane, int g, int& c, int nc,
@@ -98,26 +121,27 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
   using V = typename T::V;
   float s0 = 0.0f, s1 = 0.0f;
   const V bb = T::bias_b(g);
+  typename T::Acc prev = {};
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb) {
     const bool pre = c + 1 < nc;
     if (pre)
-      load_chunk<C::CH, C::NW>(hidden + (size_t)(c + 1) * C::CH, ring + ((c + 1) & 1) * C::CH,
-                               wave, lane);
-    const char* slot = ring + (c & 1) * C::CH;
-    typename T::Acc acc = {};
-#pragma unroll
-    for (int s = 0; s < C::KS; ++s) {
-      const V a = *(const V*)(slot + (s * 64 + lane) * T::VB);
-      acc = T::mma(a, in[s], acc);
+      load_chunk<C::CH, C::NW>(hidden + (size_t)(c + 1) * C::CH,
+                               ring + ((c + 1) % C::NSLOT) * C::CH, wave, lane);
+    const typename T::Acc acc = block_mma<PREC, WP>(ring + (c % C::NSLOT) * C::CH, lane, in, bb);
+    if (rb > 0) {
+      epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, g, rb - 1,
+                            prev, out, s0, s1);
+      pin_block<PREC, C::KS>(out, rb - 1, s0, s1);
     }
-    acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb, acc);
-    epilogue<PREC, C::KS>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1);
-    pin_block<PREC, C::KS>(out, rb, s0, s1);
     if (pre) wait_chunk();
     __syncthreads();
+    prev = acc;
     ++c;
   }
+  epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, g, C::RB - 1,
+                        prev, out, s0, s1);
+  pin_block<PREC, C::KS>(out, C::RB - 1, s0, s1);
   return add_tail<PREC>(y, s0, s1, c0, c1);
 }
 
@@ -165,15 +189,23 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
 
   V actA[C::KS], actB[C::KS];
   float s0 = 0.0f, s1 = 0.0f;
+  // layer 1, pipelined like the hidden layers: MFMAs of block rb with the
+  // epilogue of block rb-1
+  typename T::Acc prev = {};
 #pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb) {
-    const char* ch = l1 + rb * C::L1C;
+  for (int rb = 0; rb <= C::RB; ++rb) {
     typename T::Acc acc = {};
+    if (rb < C::RB) {
+      const char* ch = l1 + rb * C::L1C;
 #pragma unroll
-    for (int st = 0; st < T::L1S; ++st)
-      acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
-    epilogue<PREC, C::KS>(ch + T::L1S * 256, g, rb, acc, actA, s0, s1);
-    pin_block<PREC, C::KS>(actA, rb, s0, s1);
+      for (int st = 0; st < T::L1S; ++st)
+        acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
+    }
+    if (rb > 0) {
+      epilogue<PREC, C::KS>(l1 + (rb - 1) * C::L1C + T::L1S * 256, g, rb - 1, prev, actA, s0, s1);
+      pin_block<PREC, C::KS>(actA, rb - 1, s0, s1);
+    }
+    prev = acc;
   }
   float y = add_tail<PREC>(0.0f, s0, s1, M.c0[0], M.c1[0]);
 
@@ -191,6 +223,8 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
     y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, M.c0[j],
                                M.c1[j]);
   }
+  // the last epilogue read a ring slot the next tile's first load may reuse
+  if (nc > 0) __syncthreads();
   if (g == 0 && ok) sdf[gi] = y;
 }
 
@@ -206,7 +240,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
   constexpr int Q = C::Q;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
   char* ring = lds;
-  char* l1 = lds + 2 * C::CH;
+  char* l1 = lds + C::NSLOT * C::CH;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   load_layer1<PREC, WP>(a.m, l1, tid);
   __syncthreads();
@@ -232,7 +266,7 @@ template <int PREC, int WP>
 __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp_batch(BatchArgs a) {
   using C = Cfg<PREC, WP>;
   constexpr int Q = C::Q;
-  __shared__ __attribute__((aligned(16))) char ring[2 * C::CH];
+  __shared__ __attribute__((aligned(16))) char ring[C::NSLOT * C::CH];
   __shared__ __attribute__((aligned(16))) char l1[C::L1B];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint64_t cur = 0;   // address of the model whose layer 1 is in LDS
