@@ -91,9 +91,8 @@ __device__ __forceinline__ void fwd_epilogue(const char* tails, int g, int rb,
   float h[T::NR], cs[T::NR];
 #pragma unroll
   for (int i = 0; i < T::NR / 4; ++i) {
-    const int row = T::tail_row(i, g);
-    const f32x4 ta = *(const f32x4*)(tails + row * 4);
-    const f32x4 tb = *(const f32x4*)(tails + (T::BM + row) * 4);
+    const f32x4 ta = T::tail_vec(tails, 0, i, g);
+    const f32x4 tb = T::tail_vec(tails, 1, i, g);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int e = 4 * i + k;
@@ -189,11 +188,13 @@ __device__ __forceinline__ void adj_fwd_layer(const char* __restrict__ hidden, c
       load_chunk<C::CH, C::NW>(hidden + (size_t)(c + 1) * C::CH, ring + ((c + 1) & 1) * A::SLOT,
                                wave, lane);
     const char* slot = ring + (c & 1) * A::SLOT;
-    typename T::Acc acc = {};
+    // bias step first, then the K steps: the forward kernel's order, so the
+    // recomputed values are bit-identical to a plain query
+    typename T::Acc acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb,
+                                 typename T::Acc{});
 #pragma unroll
     for (int s = 0; s < C::KS; ++s)
       acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
-    acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb, acc);
     fwd_epilogue<PREC, C::KS>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
                               stash_at<PREC, WP>(stash, j, rb));
     if (pre) wait_chunk();

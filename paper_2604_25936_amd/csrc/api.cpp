@@ -195,18 +195,18 @@ float from_16(uint16_t v, int prec) {
 
 // Host-side geometry of the packed layout (mirrors the kernel's Tr/Cfg).
 struct Geo {
-  int BM, L1S, VB, KPS;
+  int BM, L1S, VB, KPS, TAILB;
   int RB, KS, CH, L1C;
   Geo(int prec, int WP) {
     if (prec == PREC_FP32) {
-      BM = 16; L1S = 1; VB = 4; KPS = 4;
+      BM = 16; L1S = 1; VB = 4; KPS = 4; TAILB = BM * 8;
     } else {
-      BM = 32; L1S = 2; VB = 16; KPS = 16;
+      BM = 32; L1S = 2; VB = 16; KPS = 16; TAILB = 2 * 64 * 4;
     }
     RB = WP / BM;
     KS = WP / KPS;
-    CH = (KS + 1) * 64 * VB + BM * 8;
-    L1C = L1S * 256 + BM * 8;
+    CH = (KS + 1) * 64 * VB + TAILB;
+    L1C = L1S * 256 + TAILB;
   }
 };
 
@@ -217,11 +217,22 @@ std::vector<char> pack(const Blob& B, int prec, int WP) {
   const size_t total = (size_t)G.RB * G.L1C + (size_t)(B.L - 1) * G.RB * G.CH;
   std::vector<char> buf(total, 0);
   const double s1 = (double)B.om[0] / kTwoPi, sh = (double)B.om[1] / kTwoPi;
+  auto tail_w = [&](int f, int layer, int u) {
+    const float* a = f == 0 ? B.a0[layer] : B.a1[layer];
+    return (u < W && a) ? a[u] : 0.0f;
+  };
   auto tails = [&](float* dst, int layer, int rb) {
-    for (int i = 0; i < G.BM; ++i) {
-      const int u = G.BM * rb + i;
-      dst[i] = u < W ? B.a0[layer][u] : 0.0f;
-      dst[G.BM + i] = (u < W && B.a1[layer]) ? B.a1[layer][u] : 0.0f;
+    if (prec == PREC_FP32) {
+      // a0[BM], a1[BM] in unit order
+      for (int i = 0; i < G.BM; ++i)
+        for (int f = 0; f < 2; ++f) dst[f * G.BM + i] = tail_w(f, layer, G.BM * rb + i);
+    } else {
+      // lane-indexed: lane l holds the unit of its register e = l & 15 in
+      // row group l >> 5 (accumulator row 8 (e / 4) + 4 (l / 32) + e % 4)
+      for (int l = 0; l < 64; ++l) {
+        const int e = l & 15, row = 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
+        for (int f = 0; f < 2; ++f) dst[f * 64 + l] = tail_w(f, layer, G.BM * rb + row);
+      }
     }
   };
   // layer 1

@@ -40,6 +40,11 @@ struct Tr<PREC_FP32> {
   __device__ __forceinline__ static V bias_b(int g) { return g == 0 ? 1.0f : 0.0f; }
   // offset (in floats) of the 4 tail rows that registers 4i..4i+3 hold
   __device__ __forceinline__ static int tail_row(int i, int g) { return 4 * g; }
+  // forward-chunk tail weights: a0[BM], a1[BM] in unit order
+  static constexpr int TAILB = BM * 8;
+  __device__ __forceinline__ static f32x4 tail_vec(const char* tails, int f, int i, int g) {
+    return *(const f32x4*)(tails + (f * BM + tail_row(i, g)) * 4);
+  }
   template <int KS>
   __device__ __forceinline__ static void put(V (&act)[KS], int rb, int e, float v) {
     act[4 * rb + e] = v;
@@ -86,6 +91,14 @@ struct Tr16 {
     return step == 0 ? (g == 0 ? x : y) : (g == 0 ? z : 1.0f);
   }
   __device__ __forceinline__ static int tail_row(int i, int g) { return 8 * i + 4 * g; }
+  // forward-chunk tail weights, lane-indexed: for factor f, lane l holds the
+  // weight of the unit in its own register e = l & 15 (row group g = l >> 5),
+  // i.e. a_f[tail_row(e / 4, g) + e % 4]; a DPP row broadcast of lane e then
+  // hands every lane of a 16-lane row the weight of its register e.
+  static constexpr int TAILB = 2 * 64 * 4;
+  __device__ __forceinline__ static f32x4 tail_vec(const char* tails, int f, int i, int g) {
+    return *(const f32x4*)(tails + (f * 64 + 32 * g + 4 * i) * 4);
+  }
   __device__ __forceinline__ static float lane_sum(float v) { return v + __shfl_xor(v, 32); }
 };
 
@@ -143,11 +156,11 @@ struct Cfg {
   static constexpr int KS = RB * T::SPB;        // K steps of a hidden product
   // forward chunk: KS weight steps + 1 bias step, then tail weights
   static constexpr int TAIL_OFF = (KS + 1) * 64 * T::VB;
-  static constexpr int CH = TAIL_OFF + T::BM * 8;
+  static constexpr int CH = TAIL_OFF + T::TAILB;
   // adjoint chunk (transposed weights, no bias), then tail weights
   static constexpr int TAIL_OFF_B = KS * 64 * T::VB;
   static constexpr int CH_B = TAIL_OFF_B + T::BM * 8;
-  static constexpr int L1C = T::L1S * 256 + T::BM * 8;   // layer-1 chunk bytes
+  static constexpr int L1C = T::L1S * 256 + T::TAILB;    // layer-1 chunk bytes
   static constexpr int L1B = RB * L1C;
   static constexpr int NSLOT = 3;                        // forward LDS ring slots
   static constexpr int LDS = NSLOT * CH + L1B;

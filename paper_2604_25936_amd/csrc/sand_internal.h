@@ -7,12 +7,15 @@
 //   BM units (BM = 16 for FP32, 32 for BF16/FP16). Each (layer, block) pair
 //   is one "chunk": the MFMA A-operand tiles of that block in exactly the
 //   per-lane order the kernel reads them, followed by the block's FP32 tail
-//   weights a0[BM], a1[BM]:
+//   weights: a0[BM], a1[BM] in unit order for FP32 (128 B); for BF16/FP16
+//   a0[64], a1[64] indexed by lane, lane l holding the weight of the unit in
+//   its accumulator register l & 15 (row 8 ((l & 15) / 4) + 4 (l / 32) +
+//   l % 4 of the block), 512 B:
 //
 //     layer 1, FP32 path (16x16x4 FP32 MFMA, K = 4 = x, y, z, bias):
 //        float A[1 step][64 lanes], then tails             256 + 128 B
 //     layer 1, BF16/FP16 path (32x32x2 FP32 MFMA, 2 K steps):
-//        float A[2 steps][64 lanes], then tails            512 + 256 B
+//        float A[2 steps][64 lanes], then tails            512 + 512 B
 //     layer j >= 2, FP32 (16x16x4 MFMA, WP/4 K steps + 1 bias step):
 //        float A[WP/4 + 1][64 lanes], then tails
 //     layer j >= 2, BF16/FP16 (32x32x16 MFMA, WP/16 K steps + 1 bias step):

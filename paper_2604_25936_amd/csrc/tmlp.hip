@@ -40,24 +40,59 @@ namespace {
 
 using namespace mfma;
 
+// Tail partial sums of one 32-unit block for BF16/FP16: s0 += a0[unit(e)]
+// h_e and s1 += a1[unit(e)] h_e over the lane's 16 registers, with each
+// weight taken by a DPP row broadcast (row_newbcast:e) of the lane-indexed
+// weights w0, w1, so the whole block reads 512 bytes of tail weights from
+// LDS instead of 128 bytes per lane. The leading s_nop covers the wait
+// states a DPP read needs after a VALU (or sine) write of its inputs, the
+// trailing one those of whatever reads s0, s1 next.
+__device__ __forceinline__ void tail_fma16(float& s0, float& s1, float w0, float w1,
+                                           const float (&h)[16]) {
+#define SAND_TAIL_E(E, R)                                                                   \
+  "v_fmac_f32_dpp %0, %2, %" #R " row_newbcast:" #E " row_mask:0xf bank_mask:0xf\n\t"  \
+  "v_fmac_f32_dpp %1, %3, %" #R " row_newbcast:" #E " row_mask:0xf bank_mask:0xf\n\t"
+  asm("s_nop 1\n\t"
+      SAND_TAIL_E(0, 4) SAND_TAIL_E(1, 5) SAND_TAIL_E(2, 6) SAND_TAIL_E(3, 7)
+      SAND_TAIL_E(4, 8) SAND_TAIL_E(5, 9) SAND_TAIL_E(6, 10) SAND_TAIL_E(7, 11)
+      SAND_TAIL_E(8, 12) SAND_TAIL_E(9, 13) SAND_TAIL_E(10, 14) SAND_TAIL_E(11, 15)
+      SAND_TAIL_E(12, 16) SAND_TAIL_E(13, 17) SAND_TAIL_E(14, 18) SAND_TAIL_E(15, 19)
+      "s_nop 1"
+      : "+v"(s0), "+v"(s1)
+      : "v"(w0), "v"(w1), "v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "v"(h[4]), "v"(h[5]),
+        "v"(h[6]), "v"(h[7]), "v"(h[8]), "v"(h[9]), "v"(h[10]), "v"(h[11]), "v"(h[12]),
+        "v"(h[13]), "v"(h[14]), "v"(h[15]));
+#undef SAND_TAIL_E
+}
+
 // Epilogue of one output block: sine, tail partial sums, pack for the next layer.
 template <int PREC, int KS>
-__device__ __forceinline__ void epilogue(const char* tails, int g, int rb,
+__device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int rb,
                                          const typename Tr<PREC>::Acc& acc,
                                          typename Tr<PREC>::V (&out)[KS], float& s0, float& s1) {
   using T = Tr<PREC>;
+  if constexpr (T::VB == 16) {
+    const float w0 = ((const float*)tails)[lane];
+    const float w1 = ((const float*)tails)[64 + lane];
+    float h[16];
 #pragma unroll
-  for (int i = 0; i < T::NR / 4; ++i) {
-    const int row = T::tail_row(i, g);
-    const f32x4 ta = *(const f32x4*)(tails + row * 4);
-    const f32x4 tb = *(const f32x4*)(tails + (T::BM + row) * 4);
+    for (int e = 0; e < 16; ++e) h[e] = sin_rev(acc[e]);
+    tail_fma16(s0, s1, w0, w1, h);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = 4 * i + k;
-      const float v = sin_rev(acc[e]);
-      s0 = fmaf(ta[k], v, s0);
-      s1 = fmaf(tb[k], v, s1);
-      T::template put<KS>(out, rb, e, v);
+    for (int e = 0; e < 16; ++e) T::template put<KS>(out, rb, e, h[e]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < T::NR / 4; ++i) {
+      const f32x4 ta = T::tail_vec(tails, 0, i, g);
+      const f32x4 tb = T::tail_vec(tails, 1, i, g);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = 4 * i + k;
+        const float v = sin_rev(acc[e]);
+        s0 = fmaf(ta[k], v, s0);
+        s1 = fmaf(tb[k], v, s1);
+        T::template put<KS>(out, rb, e, v);
+      }
     }
   }
 }
@@ -130,7 +165,8 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
                                ring + ((c + 1) % C::NSLOT) * C::CH, wave, lane);
     const typename T::Acc acc = block_mma<PREC, WP>(ring + (c % C::NSLOT) * C::CH, lane, in, bb);
     if (rb > 0) {
-      epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, g, rb - 1,
+      epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, lane, g,
+                            rb - 1,
                             prev, out, s0, s1);
       pin_block<PREC, C::KS>(out, rb - 1, s0, s1);
     }
@@ -139,7 +175,8 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
     prev = acc;
     ++c;
   }
-  epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, g, C::RB - 1,
+  epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, lane, g,
+                        C::RB - 1,
                         prev, out, s0, s1);
   pin_block<PREC, C::KS>(out, C::RB - 1, s0, s1);
   return add_tail<PREC>(y, s0, s1, c0, c1);
@@ -202,7 +239,8 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
         acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
     }
     if (rb > 0) {
-      epilogue<PREC, C::KS>(l1 + (rb - 1) * C::L1C + T::L1S * 256, g, rb - 1, prev, actA, s0, s1);
+      epilogue<PREC, C::KS>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1, prev, actA, s0,
+                            s1);
       pin_block<PREC, C::KS>(actA, rb - 1, s0, s1);
     }
     prev = acc;
