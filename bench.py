@@ -74,27 +74,134 @@ def time_steps(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(blob, dmap, n_sample, target_s=12.0):
+def cpu_model_name():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(blob, dmap, n_sample, target_s=12.0, n_single=1 << 16):
     """The oracle on a uniform sample of the workload; the sample grows
-    (up to 2^21 points) until it takes roughly target_s seconds."""
+    (up to 2^21 points) until it takes roughly target_s seconds. A smaller
+    sample is also timed with one BLAS thread."""
     import oracle
     import synth
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
     model = oracle.parse_blob(blob)
-    while True:
-        idx = synth.sample_indices(G ** 3, n_sample, seed=5)
-        x = synth.grid_points_at(G, idx)
+
+    def run(n):
+        x = synth.grid_points_at(G, synth.sample_indices(G ** 3, n, seed=5))
         t0 = time.perf_counter()
         d = oracle.lookup_depth(x, dmap, L)
         oracle.forward(model, x, d)
-        dt = time.perf_counter() - t0
+        return time.perf_counter() - t0
+
+    while True:
+        dt = run(n_sample)
         if dt >= target_s / 3 or n_sample >= 1 << 21:
             break
         n_sample = min(1 << 21, n_sample * max(2, 1 << int(target_s / max(dt, 1e-3)).bit_length() - 1))
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        dt1 = run(n_single)
     return {"value": n_sample / dt, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_sample} uniformly sampled cells of the 512^3 grid, same model and "
-                      f"map, FP64 numpy (lookup + adaptive forward), {dt:.1f} s"}
+                      f"map, FP64 numpy (lookup + adaptive forward), {dt:.1f} s",
+            "cpu_model": cpu_model_name(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": n_single / dt1, "unit": "queries/s",
+                              "sample": f"{n_single} cells, one BLAS thread, {dt1:.1f} s"}}
+
+
+def valu_estimate(depth_hist, width):
+    """Algorithmic vector work of one step beside the MFMA work: one sine per
+    unit per evaluated layer, and the FP32 tail dot products (tail 1 linear:
+    W FMAs; each multiplicative tail: 2W FMAs). Times are at MI355X's vector
+    rates for this instruction mix: FP32 FMA without packing, 78.6 TFLOP/s;
+    v_sin_f32 at a quarter of the FMA lane rate."""
+    sines = sum(int(c) * width * d for d, c in enumerate(depth_hist))
+    tail_flop = sum(int(c) * (2 * width + 4 * width * max(d - 1, 0))
+                    for d, c in enumerate(depth_hist) if d > 0)
+    fma_lanes_per_s = 78.6e12 / 2
+    return {"sines": sines, "sine_ms_at_peak": sines / (fma_lanes_per_s / 4) * 1e3,
+            "tail_fp32_flop": tail_flop, "tail_ms_at_peak": tail_flop / 78.6e12 * 1e3}
+
+
+def torch_leg(torch, params, xyz, depth, chunk=1 << 20):
+    """The same T-MLP in plain PyTorch FP32 on the same GPU (rocBLAS GEMMs,
+    elementwise sine and tails), as context: every point to full depth, and
+    adaptive by evaluating layer j only for the points whose exit depth is
+    at least j (the points sorted by depth once, so each layer's active set
+    is a prefix). Returns timings and the largest difference from the HIP
+    kernel's FP32 full-depth result on the first chunk."""
+    dev = xyz.device
+    n = xyz.shape[0]
+    f = lambda a: torch.as_tensor(a, dtype=torch.float32, device=dev)
+    WsT = [f(w).t().contiguous() for w in params["weights"]]   # [in, out]
+    bs = [f(b) for b in params["biases"]]
+    om = [float(params["omega_first"])] + [float(params["omega_hidden"])] * (L - 1)
+    tails = []
+    for t in params["tails"]:
+        if "a" in t:
+            tails.append((f(t["a"]), float(t["c"]), None, 1.0))
+        else:
+            tails.append((f(t["a0"]), float(t["c0"]), f(t["a1"]), float(t["c1"])))
+
+    def layer(j, h):
+        h = torch.sin(om[j] * torch.addmm(bs[j], h, WsT[j]))
+        a0, c0, a1, c1 = tails[j]
+        t = h @ a0 + c0
+        if a1 is not None:
+            t = t * (h @ a1 + c1)
+        return h, t
+
+    def full(x):
+        h, y = x, None
+        for j in range(L):
+            h, t = layer(j, h)
+            y = t if y is None else y + t
+        return y
+
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def run_full():
+        for s in range(0, n, chunk):
+            out[s:s + chunk] = full(xyz[s:s + chunk])
+
+    d_sorted, order = torch.sort(depth.to(torch.int32), descending=True)
+    counts = [int((d_sorted >= j).sum()) for j in range(1, L + 1)]
+
+    def run_adaptive():
+        res = torch.empty(n, dtype=torch.float32, device=dev)
+        for s in range(0, n, chunk):
+            idx = order[s:s + chunk]
+            x = xyz[idx]
+            h, y = x, torch.zeros(idx.shape[0], dtype=torch.float32, device=dev)
+            for j in range(L):
+                m = max(0, min(counts[j] - s, idx.shape[0]))
+                if m == 0:
+                    break
+                h, t = layer(j, h[:m])
+                y[:m] += t
+            res[idx] = y
+        return res
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_full()
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    run_adaptive()
+    torch.cuda.synchronize()
+    t_ad = time.perf_counter() - t0
+    return {"full_fp32": {"queries_per_s": n / t_full, "ms_per_step": t_full * 1e3},
+            "adaptive_fp32_masked": {"queries_per_s": n / t_ad, "ms_per_step": t_ad * 1e3},
+            "first_chunk_out": out[:chunk]}
 
 
 def _c4_inputs(k):
@@ -355,6 +462,20 @@ def main():
                 "mfma_frac": fl / (ms[3] / 1e3) / 1e12 / PEAK[prec]}
         comparisons["speedup_adaptive_bf16_vs_full_fp32"] = \
             comparisons["full_fp32"]["ms_per_step"] / (t_step * 1e3)
+        # plain PyTorch FP32 of the same model on this GPU (context)
+        try:
+            log("comparison: plain PyTorch FP32, full depth and depth-masked")
+            params = synth.siren_tmlp(MODEL_SEED, L, W, tails="mult", scale="residual")
+            tl = torch_leg(torch, params, xyz, depth)
+            ref = tl.pop("first_chunk_out")
+            sand.query(model, dm, xyz[:ref.shape[0]], out=sdf[:ref.shape[0]], precision="fp32",
+                       mode="full", workspace=ws)
+            tl["max_abs_diff_vs_hip_fp32_full_first_chunk"] = float(
+                (sdf[:ref.shape[0]] - ref).abs().max())
+            comparisons["torch"] = tl
+        except Exception as e:  # noqa: BLE001
+            log(f"torch comparison failed: {e!r}")
+            comparisons["torch"] = {"error": repr(e)}
 
     line = {
         "metric": "adaptive queries/s on 512^3 grid (8x256 SIREN T-MLP, BF16 hidden GEMMs)",
@@ -367,6 +488,7 @@ def main():
                    "points": n, "layers": L, "width": W, "map_resolution": 128,
                    "mode": "adaptive", "precision": "bf16", "parallelism": "single GPU"},
         "roofline": roofline,
+        "valu": valu_estimate(hist, W),
         "phases_ms": {k: round(float(v), 4) for k, v in
                       zip(["lookup", "scan", "scatter", "tmlp", "total"], phases.mean(axis=0))},
         "depth_histogram": [int(c) for c in hist],
