@@ -11,6 +11,9 @@ Modules:
   tmlp     -- voxel lookup, depth rule, T-MLP forward and input gradient
               (Sec. 3.1 Eq. 2-3, Sec. 3.2 Eq. 7, Sec. 3.4)
   scalar   -- a pure-Python scalar twin for tiny brute-force checks
+  depthmap -- building the network-depth map from a model (Sec. 3.2,
+              Eq. 5-7): required depth per point, sub-cell samples,
+              max-pooling per voxel, far voxels
 
 Parity status per function (what pins it) is listed in each module header.
 """
@@ -18,7 +21,8 @@ Parity status per function (what pins it) is listed in each module header.
 from .blob import parse_blob
 from .tmlp import (voxel_index, lookup_depth, forward, forward_all_tails,
                    gradient, MODE_ADAPTIVE, MODE_FULL, MODE_FORCED)
+from . import depthmap
 
 __all__ = ["parse_blob", "voxel_index", "lookup_depth", "forward",
            "forward_all_tails", "gradient", "MODE_ADAPTIVE", "MODE_FULL",
-           "MODE_FORCED"]
+           "MODE_FORCED", "depthmap"]

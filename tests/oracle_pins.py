@@ -14,6 +14,7 @@ import numpy as np
 import torch
 
 import oracle
+import oracle.depthmap as D
 import oracle.scalar
 import oracle.tmlp as T
 import synth
@@ -280,9 +281,129 @@ def check_gradient_fd(seed=31, L=3, W=10, n=60, h=1e-6):
         assert np.all(np.abs(fd - got[:, a]) <= 1e-6 * scale), "central difference"
 
 
+# -- network-depth map construction (Sec. 3.2, Eq. 5-7) ----------------------
+
+def _sign(v):
+    return (v > 0) - (v < 0)
+
+
+def required_depth_loop(row, r):
+    """Eq. 5 (near case) written out for one point, pure Python."""
+    yL = float(row[-1])
+    for i, v in enumerate(row):
+        if abs(yL - float(v)) < r and _sign(float(v)) == _sign(yL):
+            return i + 1
+    raise AssertionError("the last layer always qualifies")
+
+
+def check_required_depth_definition(seed=37, n=3000, L=6, r=0.25):
+    """Values on a lattice of r/2 (exact in binary), so ties |y_L - y_i| = r,
+    zeros and sign changes all occur."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    y = rng.integers(-6, 7, size=(n, L)).astype(np.float64) * (r / 2)
+    got = D.required_depth(y, r)
+    exp = np.array([required_depth_loop(row, r) for row in y])
+    assert np.array_equal(got, exp), f"{int((got != exp).sum())} rows differ from Eq. 5"
+
+
+def check_required_depth_extremes(L=5, r=1e-3):
+    rows = np.array([
+        [0.3] * L,                        # every layer already at y_L: depth 1
+        [1.0, 2.0, 3.0, 4.0, 5.0],        # nothing close before the last: depth L
+        [-0.3, 0.3, 0.3, 0.3, 0.3],       # right value only from layer 2
+        [0.3 + 5e-4, 0.3, -0.2, 0.3, 0.3],  # close at 1, far at 3: still depth 1 (min)
+        [-1e-4, 2e-4, 0.0, 3e-4, 5e-5],   # within r of y_L but wrong sign until layer 2
+        [0.0, 0.0, 0.0, 0.0, 0.0],        # sign(0) = sign(0): depth 1
+    ])
+    got = D.required_depth(rows, r)
+    assert list(got) == [1, L, 2, 1, 2, 1], f"got {list(got)}"
+
+
+def check_required_depth_monotone(seed=41, n=2000, L=8):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    y = np.cumsum(rng.normal(0, 1, size=(n, L)) * 0.5 ** np.arange(L), axis=1)
+    prev = None
+    for r in (1e-6, 1e-3, 1e-2, 1e-1, 1.0, 10.0):
+        d = D.required_depth(y, r)
+        assert d.min() >= 1 and d.max() <= L, "depth outside 1..L"
+        if prev is not None:
+            assert np.all(d <= prev), "a larger threshold never needs more layers"
+        prev = d
+
+
+def check_vanishing_tails(seed=43, L=6, W=12, k=3, n=400):
+    """Tails beyond layer k zero: y_i = y_k for i >= k, so d(x) <= k for any
+    r > 0, and d(x) = k when r is below every earlier gap."""
+    model = tiny_model(seed, L, W)
+    tails = list(model["tails"])
+    for j in range(k, L):
+        t = tails[j]
+        tails[j] = ("mult", np.zeros_like(t[1]), 0.0, np.zeros_like(t[3]), 0.0)
+    model = dict(model, tails=tails)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    y = T.forward_all_tails(model, x)
+    assert np.all(D.required_depth(y, 1e-3) <= k), "vanishing tails must cap the depth"
+    d = D.required_depth(y, 1e-13)
+    gaps = np.abs(y[:, k - 1:k] - y[:, :k - 1]).min(axis=1)
+    sure = gaps > 1e-12
+    assert sure.mean() > 0.99 and np.all(d[sure] == k), "depth must be exactly k"
+
+
+def check_sample_lattice(R=128, s=4, seed=45):
+    """With R = 128 and s = 4 the samples are the 512^3 grid's cell centres
+    (2m+1)/512 - 1, m = 4 i + k, each inside its voxel."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    vox = np.concatenate([[0, R ** 3 - 1, R * R * 5 + R * 7 + 3],
+                          rng.integers(0, R ** 3, size=60)])
+    pts = D.sample_points(R, vox, s)
+    assert pts.shape == (vox.size * s ** 3, 3)
+    m = (pts + 1.0) * 256.0 - 0.5
+    assert np.array_equal(m, np.round(m)), "samples off the 512^3 cell centres"
+    m = m.astype(np.int64).reshape(vox.size, s ** 3, 3)
+    ijk = np.stack([vox // (R * R), (vox // R) % R, vox % R], axis=1)
+    assert np.all(m // s == ijk[:, None, :]), "a sample outside its voxel"
+    for row in m:
+        assert len({tuple(p) for p in row}) == s ** 3, "repeated sample in a voxel"
+    first = m[:, 0, :] - s * ijk
+    assert np.all(first == 0) and np.all(m[:, -1, :] - s * ijk == s - 1)
+
+
+def check_construct_brute_force(seed=47, L=3, W=8, R=4, s=2, r=0.4):
+    """Eq. 6-7 by brute force with the scalar twin on every sample."""
+    model = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    near = rng.integers(0, 2, size=R ** 3).astype(np.uint8)
+    csdf = rng.normal(0, 0.5, size=R ** 3)
+    depth, far = D.construct(model, R, near, csdf, s, r)
+    ambiguous = 0
+    for v in range(R ** 3):
+        if not near[v]:
+            assert depth[v] == 0 and far[v] == csdf[v], f"far voxel {v}"
+            continue
+        assert far[v] == 0.0
+        i = (v // (R * R), (v // R) % R, v % R)
+        best = 0
+        for kx in range(s):
+            for ky in range(s):
+                for kz in range(s):
+                    x = [-1.0 + (2.0 / R) * (i[a] + (k + 0.5) / s)
+                         for a, k in enumerate((kx, ky, kz))]
+                    ys = [oracle.scalar.forward_point(model, x, j) for j in range(1, L + 1)]
+                    if min(abs(abs(ys[-1] - yj) - r) for yj in ys) < 1e-9:
+                        ambiguous += 1
+                    best = max(best, required_depth_loop(ys, r))
+        assert depth[v] == best, f"voxel {v}: {depth[v]} vs brute force {best}"
+    assert ambiguous == 0, "a sample sits on the threshold; pick another r"
+    assert len(set(depth[near == 1].tolist())) > 1, "the case should exercise several depths"
+
+
 ALL_CHECKS = [
     lambda: [check_cell_rule(R) for R in (2, 4, 32, 128)],
     check_textbook_mlp, check_quadratic_form, check_truncation,
     check_accumulation, check_scalar_twin, check_mpmath, check_lod_and_far,
     check_gradient_autograd, check_gradient_fd,
+    check_required_depth_definition, check_required_depth_extremes,
+    check_required_depth_monotone, check_vanishing_tails, check_sample_lattice,
+    check_construct_brute_force,
 ]

@@ -7,6 +7,7 @@ passes only if at least one of the checks in ``oracle_pins`` then fails.
 import numpy as np
 import pytest
 
+import oracle.depthmap as D
 import oracle.tmlp as T
 import oracle_pins as P
 
@@ -116,6 +117,54 @@ def _gradient_no_intermediate_tails(model, xyz, d):
 _ORIG_FORWARD = T.forward
 _ORIG_GRADIENT = T.gradient
 
+
+# -- depth-map construction mutants --------------------------------------------
+
+def _depth_inclusive(y_all, r):
+    y = np.asarray(y_all, dtype=np.float64)
+    ok = (np.abs(y[:, -1:] - y) <= r) & (np.sign(y) == np.sign(y[:, -1:]))
+    return np.argmax(ok, axis=1) + 1
+
+
+def _depth_no_sign(y_all, r):
+    y = np.asarray(y_all, dtype=np.float64)
+    return np.argmax(np.abs(y[:, -1:] - y) < r, axis=1) + 1
+
+
+def _depth_zero_based(y_all, r):
+    return _ORIG_REQUIRED(y_all, r) - 1
+
+
+def _depth_against_previous(y_all, r):
+    y = np.asarray(y_all, dtype=np.float64)
+    ref = y[:, -2:-1]
+    ok = (np.abs(ref - y) < r) & (np.sign(y) == np.sign(ref))
+    ok[:, -1] = True
+    return np.argmax(ok, axis=1) + 1
+
+
+def _samples_at_corners(R, voxels, s):
+    return _ORIG_SAMPLES(R, voxels, s) - (1.0 / (R * s))
+
+
+def _min_pooling(model, R, voxels, s, r):
+    v = np.asarray(voxels, dtype=np.int64)
+    if v.size == 0:
+        return np.zeros(0, dtype=np.int64)
+    y = T.forward_all_tails(model, D.sample_points(R, v, s))
+    return D.required_depth(y, r).reshape(v.size, s ** 3).min(axis=1)
+
+
+def _far_keeps_depth(model, R, near, center_sdf, s, r):
+    depth, far = _ORIG_CONSTRUCT(model, R, np.ones_like(np.asarray(near)), center_sdf, s, r)
+    near = np.asarray(near).reshape(-1).astype(bool)
+    return depth, np.where(near, 0.0, np.asarray(center_sdf, dtype=np.float64))
+
+
+_ORIG_REQUIRED = D.required_depth
+_ORIG_SAMPLES = D.sample_points
+_ORIG_CONSTRUCT = D.construct
+
 MUTANTS = {
     "tail biases swapped": ("_tail", _swapped_biases),
     "tail factors added": ("_tail", _additive_tail),
@@ -127,13 +176,21 @@ MUTANTS = {
     "cell by rounding": ("voxel_index", _cell_round),
     "tail gradient factors swapped": ("_tail_grad", _tail_grad_swapped),
     "gradient drops intermediate tails": ("gradient", _gradient_no_intermediate_tails),
+    "depth threshold inclusive": (D, "required_depth", _depth_inclusive),
+    "depth ignores the sign test": (D, "required_depth", _depth_no_sign),
+    "depth zero-based": (D, "required_depth", _depth_zero_based),
+    "depth against y_(L-1)": (D, "required_depth", _depth_against_previous),
+    "samples at sub-cell corners": (D, "sample_points", _samples_at_corners),
+    "min-pooling over a voxel": (D, "voxel_depths", _min_pooling),
+    "far voxels keep a depth": (D, "construct", _far_keeps_depth),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_some_pin_catches(name, monkeypatch):
-    attr, fn = MUTANTS[name]
-    monkeypatch.setattr(T, attr, fn)
+    entry = MUTANTS[name]
+    mod, attr, fn = entry if len(entry) == 3 else (T, *entry)
+    monkeypatch.setattr(mod, attr, fn)
     caught = []
     for check in P.ALL_CHECKS:
         try:

@@ -44,3 +44,29 @@ def test_gradient_matches_torch_autograd():
 
 def test_gradient_matches_central_differences():
     P.check_gradient_fd()
+
+
+# network-depth map construction (Sec. 3.2, Eq. 5-7)
+
+def test_required_depth_is_eq5_written_out():
+    P.check_required_depth_definition()
+
+
+def test_required_depth_hand_cases():
+    P.check_required_depth_extremes()
+
+
+def test_required_depth_range_and_monotone_in_r():
+    P.check_required_depth_monotone()
+
+
+def test_vanishing_tails_cap_the_depth():
+    P.check_vanishing_tails()
+
+
+def test_samples_are_the_512_grid_cell_centres():
+    P.check_sample_lattice()
+
+
+def test_map_matches_brute_force_scalar_twin():
+    P.check_construct_brute_force()
