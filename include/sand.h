@@ -126,6 +126,42 @@ sand_status sand_build_depthmap(sand_model model, const uint8_t* depth_host,
 /* Free a map (before or after its model; queries using it must be done). */
 void sand_free_depthmap(sand_depthmap map);
 
+/* What sand_construct_depthmap did. */
+typedef struct {
+  int64_t near_voxels;     /* voxels with near_host != 0 */
+  int64_t samples;         /* near_voxels * s^3 points run to full depth */
+  int32_t depth_counts[17];/* voxels per stored depth 0..16 */
+} sand_map_info;
+
+/* Build a network-depth map from `model` on the GPU (Sec. 3.2: Eq. 5
+ * required depth, Eq. 6 max-pooling per voxel, Eq. 7 far voxels).
+ *  near_host:  host uint8 [R][R][R] (C order as above): nonzero marks a
+ *              voxel that meets the surface (the paper tests whether the
+ *              distance from the voxel centre to the shape is at most half
+ *              the voxel diagonal); the caller decides.
+ *  center_sdf_host: host float32 [R][R][R], the shape's signed distance at
+ *              each voxel centre, stored for far voxels (Eq. 7).
+ *  R:          power of two, 2..1024.
+ *  s:          samples per axis, 1, 2, 4 or 8: each near voxel is sampled at
+ *              the s^3 centres of its sub-cells, -1 + (2/R)(i + (k + 1/2)/s)
+ *              per axis (exact in float32). With R = 128 and s = 4 these
+ *              are the 512^3 grid's cell centres.
+ *  r:          error threshold of Eq. 5 (> 0; the paper uses 1.5e-4).
+ *  precision:  arithmetic of the full-depth pass (FP32 recommended: the
+ *              decisions compare outputs against r).
+ * A near voxel stores max over its samples of
+ *   d(x) = min { i : |y_L(x) - y_i(x)| < r and sign(y_i(x)) = sign(y_L(x)) }
+ * (1..L), with far value 0; a far voxel stores depth 0 and its centre SDF.
+ * Blocking: runs on `stream`, waits for it, and returns the map (*out) and,
+ * when depth_host / info are not NULL, a host copy [R^3] and the counts.
+ * Errors: SAND_ERR_INVALID (null pointers, bad R, s or r, precision),
+ * SAND_ERR_NOMEM / SAND_ERR_DEVICE. */
+sand_status sand_construct_depthmap(sand_model model, const uint8_t* near_host,
+                                    const float* center_sdf_host, int32_t R,
+                                    int32_t s, float r, int32_t precision,
+                                    void* stream, sand_depthmap* out,
+                                    uint8_t* depth_host, sand_map_info* info);
+
 /* ---- queries ------------------------------------------------------------- */
 
 /* Bytes of device scratch a query of n points needs (same for the gradient). */

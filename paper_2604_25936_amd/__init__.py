@@ -6,10 +6,12 @@ served by hand-written HIP kernels behind the C ABI of include/sand.h.
 This package is the Python binding of that library.
 """
 
-from .sand import (Model, DepthMap, Server, SandError, load_model, build_depthmap, query,
+from .sand import (Model, DepthMap, Server, SandError, load_model, build_depthmap,
+                   construct_depthmap, query,
                    query_timed, query_grad, query_workspace_size,
                    query_grad_workspace_size, library, PRECISIONS, MODES)
 
-__all__ = ["Model", "DepthMap", "Server", "SandError", "load_model", "build_depthmap", "query",
+__all__ = ["Model", "DepthMap", "Server", "SandError", "load_model", "build_depthmap",
+           "construct_depthmap", "query",
            "query_timed", "query_grad", "query_workspace_size",
            "query_grad_workspace_size", "library", "PRECISIONS", "MODES"]

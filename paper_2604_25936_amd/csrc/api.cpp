@@ -508,6 +508,144 @@ extern "C" void sand_free_depthmap(sand_depthmap dm) {
   delete dm;
 }
 
+// ---------------------------------------------------- map construction --
+
+namespace {
+
+// Device buffers of one construction, freed together.
+struct DevBufs {
+  std::vector<void*> p;
+  template <class T>
+  hipError_t get(T** out, size_t bytes) {
+    *out = nullptr;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes > 0 ? bytes : 1);
+    if (e == hipSuccess) {
+      p.push_back(q);
+      *out = (T*)q;
+    }
+    return e;
+  }
+  void release() {
+    for (void* q : p) (void)hipFree(q);
+    p.clear();
+  }
+  ~DevBufs() { release(); }
+};
+
+constexpr int64_t kMapChunk = 1 << 24;   // samples per full-depth pass
+
+}  // namespace
+
+extern "C" sand_status sand_construct_depthmap(sand_model m, const uint8_t* near_host,
+                                               const float* center_sdf_host, int32_t R,
+                                               int32_t sps, float r, int32_t precision,
+                                               void* stream, sand_depthmap* out,
+                                               uint8_t* depth_host, sand_map_info* info) {
+  const char* who = "sand_construct_depthmap";
+  if (!m || !near_host || !center_sdf_host || !out)
+    return fail(SAND_ERR_INVALID, "%s: null model, mask, centre values or out", who);
+  *out = nullptr;
+  if (R < 2 || R > 1024 || (R & (R - 1)) != 0)
+    return fail(SAND_ERR_INVALID, "%s: R=%d is not a power of two in 2..1024", who, R);
+  if (sps != 1 && sps != 2 && sps != 4 && sps != 8)
+    return fail(SAND_ERR_INVALID, "%s: s=%d is not 1, 2, 4 or 8", who, sps);
+  if (!(r > 0.0f) || !std::isfinite(r))
+    return fail(SAND_ERR_INVALID, "%s: threshold r must be finite and > 0", who);
+  if (precision < 0 || precision > 2)
+    return fail(SAND_ERR_INVALID, "%s: precision %d", who, precision);
+  const int64_t cells = (int64_t)R * R * R;
+  int64_t nnear = 0;
+  for (int64_t v = 0; v < cells; ++v) nnear += near_host[v] != 0;
+  const int64_t s3 = (int64_t)sps * sps * sps, nsamp = nnear * s3;
+  if (nnear > 2147483647LL)
+    return fail(SAND_ERR_INVALID, "%s: %lld near voxels", who, (long long)nnear);
+  DeviceGuard guard(m->device);
+  if (!guard.ok) return fail(SAND_ERR_DEVICE, "%s: cannot select device", who);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t chunk = nsamp < kMapChunk ? nsamp : kMapChunk;
+  const int L = m->L;
+  DevBufs tmp;
+  uint8_t *near_d = nullptr, *depth_d = nullptr;
+  float *csdf_d = nullptr, *far_d = nullptr, *xyz = nullptr, *yall = nullptr, *ylast = nullptr;
+  int32_t* list = nullptr;
+  uint32_t *count = nullptr, *depth32 = nullptr;
+  hipError_t e = tmp.get(&near_d, cells);
+  if (e == hipSuccess) e = tmp.get(&csdf_d, cells * 4);
+  if (e == hipSuccess) e = tmp.get(&list, nnear * 4);
+  if (e == hipSuccess) e = tmp.get(&count, 4);
+  if (e == hipSuccess) e = tmp.get(&depth32, cells * 4);
+  if (e == hipSuccess) e = tmp.get(&xyz, chunk * 12);
+  if (e == hipSuccess) e = tmp.get(&yall, chunk * L * 4);
+  if (e == hipSuccess) e = tmp.get(&ylast, chunk * 4);
+  if (e != hipSuccess) return fail(SAND_ERR_NOMEM, "%s: scratch for %lld samples", who,
+                                   (long long)nsamp);
+  // the map's own arrays, handed to the map object on success
+  e = hipMalloc((void**)&depth_d, cells);
+  if (e == hipSuccess) e = hipMalloc((void**)&far_d, cells * 4);
+  auto drop_map = [&]() {
+    if (depth_d) (void)hipFree(depth_d);
+    if (far_d) (void)hipFree(far_d);
+  };
+  if (e != hipSuccess) {
+    drop_map();
+    return fail(SAND_ERR_NOMEM, "%s: map of R=%d", who, R);
+  }
+  e = hipMemcpyAsync(near_d, near_host, cells, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(csdf_d, center_sdf_host, cells * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(count, 0, 4, st);
+  if (e == hipSuccess) e = hipMemsetAsync(depth32, 0, cells * 4, st);
+  if (e == hipSuccess) e = launch_map_list(near_d, cells, list, count, st);
+  QueryArgs qa{};
+  qa.m = m->args[precision];
+  qa.xyz = xyz;
+  qa.sdf = ylast;           // y_L again (also the last column of y_all)
+  qa.full_depth = L;
+  qa.y_all = yall;
+  for (int64_t first = 0; e == hipSuccess && first < nsamp; first += chunk) {
+    const int64_t k = nsamp - first < chunk ? nsamp - first : chunk;
+    e = launch_map_samples(list, first, k, R, sps, xyz, st);
+    qa.n = k;
+    if (e == hipSuccess) e = launch_tmlp(precision, qa, m->num_cu, st);
+    if (e == hipSuccess) e = launch_map_pool(yall, L, list, first, k, sps, r, depth32, st);
+  }
+  if (e == hipSuccess) e = launch_map_finish(near_d, csdf_d, depth32, cells, depth_d, far_d, st);
+  if (e == hipSuccess && depth_host)
+    e = hipMemcpyAsync(depth_host, depth_d, cells, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    drop_map();
+    return device_fail(e, "sand_construct_depthmap");
+  }
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->near_voxels = nnear;
+    info->samples = nsamp;
+    std::vector<uint8_t> h;
+    const uint8_t* dh = depth_host;
+    if (!dh) {
+      h.resize(cells);
+      e = hipMemcpy(h.data(), depth_d, cells, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        drop_map();
+        return device_fail(e, "sand_construct_depthmap: read back");
+      }
+      dh = h.data();
+    }
+    for (int64_t v = 0; v < cells; ++v) info->depth_counts[dh[v] <= 16 ? dh[v] : 16]++;
+  }
+  sand_depthmap dm = new sand_depthmap_s();
+  dm->model = m;
+  dm->device = m->device;
+  dm->R = R;
+  dm->depth = depth_d;
+  dm->far = far_d;
+  *out = dm;
+  return SAND_OK;
+}
+
 // --------------------------------------------------------------- queries --
 
 namespace sand {

@@ -82,6 +82,7 @@ struct QueryArgs {
   const Plan* plan;        // device plan, or null (FULL mode)
   int64_t n;
   int full_depth;          // FULL mode: the depth every point runs to
+  float* y_all;            // [n][L] every accumulated output y_1..y_d, or null
 };
 
 // One query of a batched launch (server). Pointers are device memory; the
@@ -135,6 +136,16 @@ hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_bucketing_batch(BatchReq* reqs, int nreq, int64_t nblk, int max_depth,
                                   int tile_q, int64_t* total_tiles, hipStream_t s);
 hipError_t launch_tmlp_batch(int prec, int WP, const BatchArgs& a, int num_cu, hipStream_t s);
+
+// network-depth map construction (mapbuild.hip)
+hipError_t launch_map_list(const uint8_t* near, int64_t cells, int32_t* list, uint32_t* count,
+                           hipStream_t s);
+hipError_t launch_map_samples(const int32_t* list, int64_t first, int64_t nsamp, int R, int sps,
+                              float* xyz, hipStream_t s);
+hipError_t launch_map_pool(const float* y_all, int L, const int32_t* list, int64_t first,
+                           int64_t nsamp, int sps, float r, uint32_t* depth32, hipStream_t s);
+hipError_t launch_map_finish(const uint8_t* near, const float* center_sdf, const uint32_t* depth32,
+                             int64_t cells, uint8_t* depth, float* far, hipStream_t s);
 
 int tmlp_tile_points(int prec);
 size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L);

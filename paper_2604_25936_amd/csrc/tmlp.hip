@@ -204,7 +204,8 @@ template <int PREC, int WP>
 __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __restrict__ xyz,
                                          float* __restrict__ sdf, const int32_t* __restrict__ perm,
                                          int64_t start, int64_t cnt, int d, char* ring,
-                                         const char* l1, int lane, int wave) {
+                                         const char* l1, int lane, int wave,
+                                         float* __restrict__ y_all) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
@@ -246,6 +247,9 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
     prev = acc;
   }
   float y = add_tail<PREC>(0.0f, s0, s1, M.c0[0], M.c1[0]);
+  // every accumulated output y_j, for building a depth map (Eq. 5)
+  float* yrow = (y_all && g == 0 && ok) ? y_all + gi * M.L : nullptr;
+  if (yrow) yrow[0] = y;
 
   const int nc = (d - 1) * C::RB;
   int c = 0;
@@ -257,9 +261,11 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
   for (int j = 2; j <= d; j += 2) {
     y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actA, actB, M.c0[j - 1],
                                M.c1[j - 1]);
+    if (yrow) yrow[j - 1] = y;
     if (j + 1 > d) break;
     y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, M.c0[j],
                                M.c1[j]);
+    if (yrow) yrow[j] = y;
   }
   // the last epilogue read a ring slot the next tile's first load may reuse
   if (nc > 0) __syncthreads();
@@ -293,7 +299,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
       start = tile * Q;
       cnt = a.n - start < Q ? a.n - start : Q;
     }
-    run_tile<PREC, WP>(a.m, a.xyz, a.sdf, a.perm, start, cnt, d, ring, l1, lane, wave);
+    run_tile<PREC, WP>(a.m, a.xyz, a.sdf, a.perm, start, cnt, d, ring, l1, lane, wave, a.y_all);
   }
 }
 
@@ -327,7 +333,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp_batch(BatchArgs a)
     int d;
     int64_t start, cnt;
     decode_tile<Q>(&q.plan, q.L, tile - q.tile0, d, start, cnt);
-    run_tile<PREC, WP>(M, q.xyz, q.sdf, q.perm, start, cnt, d, ring, l1, lane, wave);
+    run_tile<PREC, WP>(M, q.xyz, q.sdf, q.perm, start, cnt, d, ring, l1, lane, wave, nullptr);
   }
 }
 

@@ -46,6 +46,11 @@ class ReqStats(ctypes.Structure):
                 ("batch_size", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class MapInfo(ctypes.Structure):
+    _fields_ = [("near_voxels", ctypes.c_int64), ("samples", ctypes.c_int64),
+                ("depth_counts", ctypes.c_int32 * 17)]
+
+
 _lib = None
 
 
@@ -65,6 +70,8 @@ def library():
             "sand_model_info": (I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
             "sand_build_depthmap": (I32, [P, P, I32, P, ctypes.POINTER(P)]),
             "sand_free_depthmap": (None, [P]),
+            "sand_construct_depthmap": (I32, [P, P, P, I32, I32, ctypes.c_float, I32, P,
+                                              ctypes.POINTER(P), P, ctypes.POINTER(MapInfo)]),
             "sand_query_workspace_size": (SZ, [I64]),
             "sand_query_grad_workspace_size": (SZ, [P, I64, I32]),
             "sand_query": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P]),
@@ -135,7 +142,12 @@ class Model:
 class DepthMap:
     """A dense R^3 network-depth map for one model (sand_build_depthmap)."""
 
-    def __init__(self, model, depth, far=None):
+    def __init__(self, model, depth, far=None, _handle=None):
+        if _handle is not None:     # built on the device (construct_depthmap)
+            self._h = _handle
+            self.model = model
+            self.R = int(depth)
+            return
         depth = np.ascontiguousarray(depth, dtype=np.uint8)
         if depth.ndim != 3 or not (depth.shape[0] == depth.shape[1] == depth.shape[2]):
             raise ValueError("depth map must be a cube [R, R, R]")
@@ -173,6 +185,31 @@ def load_model(blob, device=0):
 
 def build_depthmap(model, depth, far=None):
     return DepthMap(model, depth, far)
+
+
+def construct_depthmap(model, near, center_sdf, s=4, r=1.5e-4, precision="fp32", stream=None):
+    """Build a network-depth map from the model on the GPU
+    (sand_construct_depthmap). near: uint8/bool [R, R, R] near-surface mask;
+    center_sdf: float [R, R, R] signed distance at voxel centres (stored for
+    far voxels). Returns (DepthMap, depth uint8 [R, R, R], info dict)."""
+    near = np.ascontiguousarray(near, dtype=np.uint8)
+    if near.ndim != 3 or not (near.shape[0] == near.shape[1] == near.shape[2]):
+        raise ValueError("near mask must be a cube [R, R, R]")
+    csdf = np.ascontiguousarray(center_sdf, dtype=np.float32)
+    if csdf.shape != near.shape:
+        raise ValueError("centre values must match the mask's shape")
+    R = near.shape[0]
+    depth = np.empty_like(near)
+    info = MapInfo()
+    h = ctypes.c_void_p()
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(library().sand_construct_depthmap(
+        model.handle, near.ctypes.data_as(ctypes.c_void_p), csdf.ctypes.data_as(ctypes.c_void_p),
+        R, int(s), float(r), p, _stream(stream), ctypes.byref(h),
+        depth.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info)))
+    dm = DepthMap(model, R, _handle=h)
+    return dm, depth, {"near_voxels": info.near_voxels, "samples": info.samples,
+                       "depth_counts": list(info.depth_counts)}
 
 
 def query_workspace_size(n):

@@ -14,7 +14,8 @@ from .blob import (MAGIC, VERSION, HEADER_BYTES, TAIL_LINEAR, TAIL_MULT,
                    write_blob, blob_nbytes)
 from .model import siren_tmlp, TailScale
 from .surface import sphere_sdf, Primitives, random_primitives
-from .depthmap import (voxel_centres, band_map_c1, band_map_c2, far_value_grid)
+from .depthmap import (voxel_centres, band_map_c1, band_map_c2, far_value_grid,
+                       near_surface_mask)
 from .queries import (grid_points, grid_points_at, sample_indices,
                       near_surface_points, slab_points, camera_ray_points)
 
@@ -22,7 +23,7 @@ __all__ = [
     "MAGIC", "VERSION", "HEADER_BYTES", "TAIL_LINEAR", "TAIL_MULT",
     "write_blob", "blob_nbytes", "siren_tmlp", "TailScale",
     "sphere_sdf", "Primitives", "random_primitives",
-    "voxel_centres", "band_map_c1", "band_map_c2", "far_value_grid",
+    "voxel_centres", "band_map_c1", "band_map_c2", "far_value_grid", "near_surface_mask",
     "grid_points", "grid_points_at", "sample_indices",
     "near_surface_points", "slab_points", "camera_ray_points",
 ]

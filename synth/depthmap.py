@@ -67,3 +67,10 @@ def band_map_c2(prims, R=128, L=8):
 def far_value_grid(sdf_fn, R):
     """FP32 grid of the surface's signed distance at each cell centre."""
     return sdf_fn(_centre_grid(R)).astype(np.float32)
+
+
+def near_surface_mask(sdf_fn, R):
+    """uint8 [R, R, R]: 1 where the cell meets the surface, by the paper's
+    test (Sec. 4.1): the distance from the cell centre to the surface is at
+    most half the cell's diagonal, sqrt(3)/R for cells of side 2/R."""
+    return (np.abs(sdf_fn(_centre_grid(R))) <= np.sqrt(3.0) / R).astype(np.uint8)

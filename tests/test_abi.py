@@ -89,6 +89,9 @@ def test_null_arguments():
     assert o.precision == 0 and o.mode == 0 and o.max_depth == 0
     assert lib.sand_query(None, None, None, 0, None, ctypes.byref(o), None) == sand.ERR_INVALID
     assert lib.sand_model_info(None, None, None) == sand.ERR_INVALID
+    info = sand.MapInfo()
+    assert lib.sand_construct_depthmap(None, None, None, 4, 2, 1e-3, 0, None, ctypes.byref(h),
+                                       None, ctypes.byref(info)) == sand.ERR_INVALID
 
 
 def test_workspace_size():
