@@ -29,7 +29,8 @@ L, W = 8, 256
 MODEL_SEED, SURFACE_SEED = 1000, 2000
 PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tmlp_bf16_512grid_traffic.json")
-KERNEL_SOURCES = ["paper_2604_25936_amd/csrc/tmlp.hip", "paper_2604_25936_amd/csrc/sand_internal.h"]
+KERNEL_SOURCES = ["paper_2604_25936_amd/csrc/tmlp.hip", "paper_2604_25936_amd/csrc/mfma_common.h",
+                  "paper_2604_25936_amd/csrc/sand_internal.h"]
 
 
 def log(msg):
@@ -407,6 +408,8 @@ def main():
                     help="'all', or a comma list of headline,compare,c3,grad,serving,mapbuild,cpu")
     ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--serving-models", type=int, default=64)
+    ap.add_argument("--headline-mode", default="adaptive", choices=["adaptive", "full"],
+                    help="mode of the timed leg (full: every point to depth L; for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
@@ -457,16 +460,19 @@ def main():
     def step(prec="bf16", mode="adaptive"):
         return lambda: sand.query(model, dm, xyz, out=sdf, precision=prec, mode=mode, workspace=ws)
 
-    log(f"headline: adaptive bf16, {args.steps} steps after {args.warmup} warm-up")
-    t_step = time_steps(step(), args.steps, args.warmup)
+    hmode = args.headline_mode
+    head_flops = full_flops if hmode == "full" else flops
+    log(f"headline: {hmode} bf16, {args.steps} steps after {args.warmup} warm-up")
+    t_step = time_steps(step(mode=hmode), args.steps, args.warmup)
     # the dominant kernel's own duration, HIP events on the launch stream
     phases = []
     for _ in range(max(3, min(args.steps, 10))):
-        _, ms = sand.query_timed(model, dm, xyz, out=sdf, precision="bf16", workspace=ws)
+        _, ms = sand.query_timed(model, dm, xyz, out=sdf, precision="bf16", mode=hmode,
+                                 workspace=ws)
         phases.append(ms)
     phases = np.array(phases)
     t_kernel = float(phases[:, 3].mean()) / 1e3
-    achieved = flops / t_kernel / 1e12
+    achieved = head_flops / t_kernel / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["bf16"],
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK["bf16"], 4),
                 "traffic": measured_traffic()}
@@ -503,7 +509,7 @@ def main():
             comparisons["torch"] = {"error": repr(e)}
 
     line = {
-        "metric": "adaptive queries/s on 512^3 grid (8x256 SIREN T-MLP, BF16 hidden GEMMs)",
+        "metric": f"{hmode} queries/s on 512^3 grid (8x256 SIREN T-MLP, BF16 hidden GEMMs)",
         "value": n / t_step, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
@@ -511,7 +517,7 @@ def main():
                                "linear, tails 2-8 multiplicative, residual-scaled); 128^3 depth "
                                "map from 12 seeded spheres/tori (bands + curvature bump)",
                    "points": n, "layers": L, "width": W, "map_resolution": 128,
-                   "mode": "adaptive", "precision": "bf16", "parallelism": "single GPU"},
+                   "mode": hmode, "precision": "bf16", "parallelism": "single GPU"},
         "roofline": roofline,
         "valu": valu_estimate(hist, W),
         "phases_ms": {k: round(float(v), 4) for k, v in
