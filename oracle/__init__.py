@@ -14,6 +14,7 @@ Modules:
   depthmap -- building the network-depth map from a model (Sec. 3.2,
               Eq. 5-7): required depth per point, sub-cell samples,
               max-pooling per voxel, far voxels
+  dynamic  -- map-free early exit on small residuals (Sec. 4.4 ablation)
 
 Parity status per function (what pins it) is listed in each module header.
 """
@@ -21,8 +22,8 @@ Parity status per function (what pins it) is listed in each module header.
 from .blob import parse_blob
 from .tmlp import (voxel_index, lookup_depth, forward, forward_all_tails,
                    gradient, MODE_ADAPTIVE, MODE_FULL, MODE_FORCED)
-from . import depthmap
+from . import depthmap, dynamic
 
 __all__ = ["parse_blob", "voxel_index", "lookup_depth", "forward",
            "forward_all_tails", "gradient", "MODE_ADAPTIVE", "MODE_FULL",
-           "MODE_FORCED", "depthmap"]
+           "MODE_FORCED", "depthmap", "dynamic"]

@@ -15,6 +15,7 @@ import torch
 
 import oracle
 import oracle.depthmap as D
+import oracle.dynamic as DY
 import oracle.scalar
 import oracle.tmlp as T
 import synth
@@ -398,6 +399,85 @@ def check_construct_brute_force(seed=47, L=3, W=8, R=4, s=2, r=0.4):
     assert len(set(depth[near == 1].tolist())) > 1, "the case should exercise several depths"
 
 
+# -- map-free dynamic early exit (Sec. 4.4 ablation) ------------------------
+
+def dynamic_exit_loop(trow, r, max_depth=0):
+    """The exit rule written out for one point, pure Python."""
+    L = len(trow)
+    d = L
+    for i in range(2, L + 1):
+        if abs(float(trow[i - 1])) < r:
+            d = i
+            break
+    return min(d, max_depth) if max_depth > 0 else d
+
+
+def check_dynamic_definition(seed=53, n=3000, L=6, r=0.25):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = rng.integers(-4, 5, size=(n, L)).astype(np.float64) * (r / 2)
+    for md in (0, 3):
+        got = DY.exit_from_tails(t, r, md)
+        exp = np.array([dynamic_exit_loop(row, r, md) for row in t])
+        assert np.array_equal(got, exp), f"{int((got != exp).sum())} rows differ (max_depth {md})"
+
+
+def check_dynamic_hand_cases(r=1e-3):
+    t = np.array([
+        [0.0, 0.0, 0.0, 0.0],      # layer 1 is never tested: exit at 2
+        [0.5, 0.5, 5e-4, 0.0],     # first small residual at 3
+        [0.5, -1e-3, 0.5, 0.5],    # |t| = r is not below r: runs to L
+        [0.5, 0.5, 0.5, 0.5],      # no small residual: L
+        [0.5, -9e-4, 0.0, 0.0],    # negative residual counts by magnitude: 2
+    ])
+    assert list(DY.exit_from_tails(t, r)) == [2, 3, 4, 4, 2]
+    assert list(DY.exit_from_tails(t[:, :1], r)) == [1] * 5, "a one-layer net exits at 1"
+
+
+def check_dynamic_monotone_and_tails(seed=55, L=6, W=12, n=300):
+    model = tiny_model(seed, L, W)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    t = DY.tails(model, x)
+    y = T.forward_all_tails(model, x)
+    assert np.allclose(np.cumsum(t, axis=1), y, rtol=0, atol=1e-12), "tails must sum to y_i"
+    prev = None
+    for r in (1e-6, 1e-2, 1e-1, 1.0, 10.0):
+        d = DY.exit_from_tails(t, r)
+        assert d.min() >= 2 and d.max() <= L
+        if prev is not None:
+            assert np.all(d <= prev), "a larger threshold never runs deeper"
+        prev = d
+    yd, dd = DY.dynamic_forward(model, x, 1e-1)
+    assert np.array_equal(dd, DY.exit_from_tails(t, 1e-1))
+    assert np.allclose(yd, y[np.arange(n), dd - 1], rtol=0, atol=1e-12)
+
+
+def check_dynamic_vanishing_tails(seed=57, L=6, W=12, k=3, n=300):
+    model = tiny_model(seed, L, W)
+    tl = list(model["tails"])
+    for j in range(k, L):
+        t = tl[j]
+        tl[j] = ("mult", np.zeros_like(t[1]), 0.0, np.zeros_like(t[3]), 0.0)
+    model = dict(model, tails=tl)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = rng.uniform(-1, 1, size=(n, 3))
+    _, d = DY.dynamic_forward(model, x, 1e-13)
+    t = DY.tails(model, x)
+    sure = (np.abs(t[:, 1:k]) > 1e-12).all(axis=1)
+    assert sure.mean() > 0.99 and np.all(d[sure] == k + 1), "exit right after the last live tail"
+
+
+def check_dynamic_scalar_twin(seed=59, L=4, W=8, r=0.3):
+    model = tiny_model(seed, L, W)
+    x = synth.grid_points(4).astype(np.float64)
+    _, d = DY.dynamic_forward(model, x, r)
+    for i, p in enumerate(x):
+        ys = [oracle.scalar.forward_point(model, p, j) for j in range(1, L + 1)]
+        tr = [ys[0]] + [ys[j] - ys[j - 1] for j in range(1, L)]
+        assert min(abs(abs(v) - r) for v in tr[1:]) > 1e-9, "sample on the threshold"
+        assert d[i] == dynamic_exit_loop(tr, r), f"point {i}"
+
+
 ALL_CHECKS = [
     lambda: [check_cell_rule(R) for R in (2, 4, 32, 128)],
     check_textbook_mlp, check_quadratic_form, check_truncation,
@@ -406,4 +486,6 @@ ALL_CHECKS = [
     check_required_depth_definition, check_required_depth_extremes,
     check_required_depth_monotone, check_vanishing_tails, check_sample_lattice,
     check_construct_brute_force,
+    check_dynamic_definition, check_dynamic_hand_cases, check_dynamic_monotone_and_tails,
+    check_dynamic_vanishing_tails, check_dynamic_scalar_twin,
 ]

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle.depthmap as D
+import oracle.dynamic as DY
 import oracle.tmlp as T
 import oracle_pins as P
 
@@ -161,6 +162,45 @@ def _far_keeps_depth(model, R, near, center_sdf, s, r):
     return depth, np.where(near, 0.0, np.asarray(center_sdf, dtype=np.float64))
 
 
+def _dyn_from_layer_one(t, r, max_depth=0):
+    t = np.asarray(t, dtype=np.float64)
+    small = np.abs(t) < r
+    small[:, -1] = True
+    d = np.argmax(small, axis=1) + 1
+    return np.minimum(d, max_depth) if max_depth > 0 else d
+
+
+def _dyn_inclusive(t, r, max_depth=0):
+    t = np.asarray(t, dtype=np.float64)
+    small = np.abs(t) <= r
+    small[:, 0] = False
+    small[:, -1] = True
+    d = np.argmax(small, axis=1) + 1
+    return np.minimum(d, max_depth) if max_depth > 0 else d
+
+
+def _dyn_on_outputs(model, xyz):
+    return T.forward_all_tails(model, xyz)          # y_i in place of t_i
+
+
+def _dyn_signed(t, r, max_depth=0):
+    return _signed_exit(t, r, max_depth)
+
+
+def _signed_exit(t, r, max_depth):
+    t = np.asarray(t, dtype=np.float64)
+    small = t < r                                   # sign kept: negative tails exit at once
+    small[:, 0] = False
+    small[:, -1] = True
+    d = np.argmax(small, axis=1) + 1
+    return np.minimum(d, max_depth) if max_depth > 0 else d
+
+
+def _dyn_no_clamp(t, r, max_depth=0):
+    return _ORIG_EXIT(t, r, 0)
+
+
+_ORIG_EXIT = DY.exit_from_tails
 _ORIG_REQUIRED = D.required_depth
 _ORIG_SAMPLES = D.sample_points
 _ORIG_CONSTRUCT = D.construct
@@ -183,6 +223,11 @@ MUTANTS = {
     "samples at sub-cell corners": (D, "sample_points", _samples_at_corners),
     "min-pooling over a voxel": (D, "voxel_depths", _min_pooling),
     "far voxels keep a depth": (D, "construct", _far_keeps_depth),
+    "dynamic test from layer 1": (DY, "exit_from_tails", _dyn_from_layer_one),
+    "dynamic threshold inclusive": (DY, "exit_from_tails", _dyn_inclusive),
+    "dynamic test on outputs": (DY, "tails", _dyn_on_outputs),
+    "dynamic residual sign kept": (DY, "exit_from_tails", _dyn_signed),
+    "dynamic ignores max_depth": (DY, "exit_from_tails", _dyn_no_clamp),
 }
 
 

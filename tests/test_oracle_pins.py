@@ -70,3 +70,25 @@ def test_samples_are_the_512_grid_cell_centres():
 
 def test_map_matches_brute_force_scalar_twin():
     P.check_construct_brute_force()
+
+
+# map-free dynamic early exit (Sec. 4.4 ablation)
+
+def test_dynamic_exit_is_the_rule_written_out():
+    P.check_dynamic_definition()
+
+
+def test_dynamic_exit_hand_cases():
+    P.check_dynamic_hand_cases()
+
+
+def test_dynamic_monotone_and_tails_sum_to_outputs():
+    P.check_dynamic_monotone_and_tails()
+
+
+def test_dynamic_exit_after_last_live_tail():
+    P.check_dynamic_vanishing_tails()
+
+
+def test_dynamic_matches_scalar_twin():
+    P.check_dynamic_scalar_twin()
