@@ -60,15 +60,20 @@ typedef enum { SAND_FP32 = 0, SAND_BF16 = 1, SAND_FP16 = 2 } sand_precision;
 /* Where the exit depth comes from:
  *  ADAPTIVE: the depth map (Sec. 3.4);
  *  FULL:     every point runs all L layers (the plain full-depth network);
- *  FORCED:   a caller-given depth per point (opts.forced_depth). */
-typedef enum { SAND_ADAPTIVE = 0, SAND_FULL = 1, SAND_FORCED = 2 } sand_mode;
+ *  FORCED:   a caller-given depth per point (opts.forced_depth);
+ *  DYNAMIC:  no map: a point stops after the first layer i >= 2 whose
+ *            residual (tail output t_i, FP32) satisfies |t_i| < opts.dynamic_r,
+ *            else runs to L (the map-free strategy of the Sec. 4.4 ablation;
+ *            t_1 is the base prediction and is not tested). */
+typedef enum { SAND_ADAPTIVE = 0, SAND_FULL = 1, SAND_FORCED = 2, SAND_DYNAMIC = 3 } sand_mode;
 
 typedef struct {
   int32_t precision;            /* sand_precision */
   int32_t mode;                 /* sand_mode */
   int32_t max_depth;            /* > 0: exit depth <- min(depth, max_depth)
                                    (level of detail, Sec. 3.4); 0: no clamp */
-  int32_t reserved;             /* must be 0 */
+  float dynamic_r;              /* DYNAMIC: residual threshold r > 0;
+                                   other modes: must be 0 */
   const uint8_t* forced_depth;  /* device [n], FORCED only: values 0..L
                                    (0 needs a map with far-field values) */
   uint8_t* depth_out;           /* device [n] or NULL: receives each

@@ -674,9 +674,14 @@ sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const f
   if (((uintptr_t)xyz & 3u) != 0) return fail(SAND_ERR_INVALID, "%s: points not 4-byte aligned", who);
   if (o.precision < 0 || o.precision > 2)
     return fail(SAND_ERR_INVALID, "%s: precision %d", who, o.precision);
-  if (o.mode < 0 || o.mode > 2) return fail(SAND_ERR_INVALID, "%s: mode %d", who, o.mode);
+  if (o.mode < 0 || o.mode > 3) return fail(SAND_ERR_INVALID, "%s: mode %d", who, o.mode);
   if (o.max_depth < 0) return fail(SAND_ERR_INVALID, "%s: max_depth %d", who, o.max_depth);
-  if (o.reserved != 0) return fail(SAND_ERR_INVALID, "%s: reserved field not zero", who);
+  if (o.mode == SAND_DYNAMIC) {
+    if (!(o.dynamic_r > 0.0f) || !std::isfinite(o.dynamic_r))
+      return fail(SAND_ERR_INVALID, "%s: dynamic mode needs a finite dynamic_r > 0", who);
+  } else if (o.dynamic_r != 0.0f) {
+    return fail(SAND_ERR_INVALID, "%s: dynamic_r is only for dynamic mode", who);
+  }
   if (dm && dm->model != m) return fail(SAND_ERR_INVALID, "%s: map belongs to another model", who);
   if (o.mode == SAND_ADAPTIVE && !dm) return fail(SAND_ERR_INVALID, "%s: adaptive mode needs a map", who);
   if (o.mode == SAND_FORCED && n > 0 && !o.forced_depth)
@@ -736,13 +741,18 @@ sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_
   qa.sdf = sdf;
   qa.n = n;
   hipError_t e;
-  if (o.mode == SAND_FULL) {
+  if (o.mode == SAND_FULL || o.mode == SAND_DYNAMIC) {
     const int d = (o.max_depth > 0 && o.max_depth < m->L) ? o.max_depth : m->L;
     qa.full_depth = d;
+    if (o.mode == SAND_DYNAMIC) {
+      qa.dyn_r = o.dynamic_r;
+      qa.depth_out = o.depth_out;
+    }
     for (int i = 0; i < 4; ++i) mark(i);
     if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
     mark(4);
-    if (o.depth_out && (e = launch_fill_u8(o.depth_out, n, (uint8_t)d, s)) != hipSuccess)
+    if (o.mode == SAND_FULL && o.depth_out &&
+        (e = launch_fill_u8(o.depth_out, n, (uint8_t)d, s)) != hipSuccess)
       return device_fail(e, "depth fill launch");
     return SAND_OK;
   }
@@ -769,7 +779,7 @@ extern "C" sand_status sand_query(sand_model m, sand_depthmap dm, const float* x
   hipStream_t s = (hipStream_t)stream;
   char* ws = (char*)o.workspace;
   bool owned = false;
-  if (o.mode != SAND_FULL && !ws) {
+  if (o.mode != SAND_FULL && o.mode != SAND_DYNAMIC && !ws) {
     hipError_t e = hipMallocAsync((void**)&ws, workspace_layout(n).total, s);
     if (e != hipSuccess) return fail(SAND_ERR_NOMEM, "sand_query: scratch of %zu bytes",
                                      workspace_layout(n).total);
@@ -800,7 +810,7 @@ extern "C" sand_status sand_query_timed(sand_model m, sand_depthmap dm, const fl
     }
   char* ws = (char*)o.workspace;
   bool owned = false;
-  if (o.mode != SAND_FULL && !ws) {
+  if (o.mode != SAND_FULL && o.mode != SAND_DYNAMIC && !ws) {
     if (hipMallocAsync((void**)&ws, workspace_layout(n).total, s) != hipSuccess) {
       for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
       return fail(SAND_ERR_NOMEM, "sand_query_timed: scratch");
@@ -830,7 +840,11 @@ extern "C" sand_status sand_query_grad(sand_model m, sand_depthmap dm, const flo
   sand_query_opts o;
   if (opts) o = *opts; else sand_query_opts_init(&o);
   sand_status st = check_query("sand_query_grad", m, dm, xyz, n, grad, o);
-  if (st != SAND_OK || n == 0) return st;
+  if (st != SAND_OK) return st;
+  if (o.mode == SAND_DYNAMIC)
+    return fail(SAND_ERR_UNSUPPORTED, "sand_query_grad: dynamic mode has no gradient path "
+                "(query with depth_out, then pass the depths in FORCED mode)");
+  if (n == 0) return st;
   const size_t need = workspace_layout(n).total + grad_stash_bytes(m, o.precision);
   if (o.workspace && o.workspace_bytes < need)
     return fail(SAND_ERR_INVALID, "sand_query_grad: workspace of %zu bytes, need %zu",

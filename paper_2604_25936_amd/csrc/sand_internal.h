@@ -83,6 +83,8 @@ struct QueryArgs {
   int64_t n;
   int full_depth;          // FULL mode: the depth every point runs to
   float* y_all;            // [n][L] every accumulated output y_1..y_d, or null
+  float dyn_r;             // > 0: map-free early exit on |t_j| < dyn_r (j >= 2)
+  uint8_t* depth_out;      // [n] exit depths (written when dyn_r > 0), or null
 };
 
 // One query of a batched launch (server). Pointers are device memory; the

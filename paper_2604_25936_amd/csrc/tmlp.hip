@@ -117,9 +117,12 @@ __device__ __forceinline__ void pin_block(const typename Tr<PREC>::V (&out)[KS],
 // Add tail t_j = u0 * u1 to the running output (u0, u1 its two factors,
 // summed over the lanes that hold the point's units).
 template <int PREC>
-__device__ __forceinline__ float add_tail(float y, float s0, float s1, float c0, float c1) {
+__device__ __forceinline__ float add_tail(float y, float s0, float s1, float c0, float c1,
+                                          float* t = nullptr) {
   using T = Tr<PREC>;
-  return fmaf(T::lane_sum(s0) + c0, T::lane_sum(s1) + c1, y);
+  const float u0 = T::lane_sum(s0) + c0, u1 = T::lane_sum(s1) + c1;
+  if (t) *t = u0 * u1;
+  return fmaf(u0, u1, y);
 }
 
 // MFMA chain of one output block: bias + W_j h over all K steps, A operands
@@ -150,7 +153,7 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
                                               int wave, int lane, int g, int& c, int nc,
                                               const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
                                               typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
-                                              float c0, float c1) {
+                                              float c0, float c1, float& t) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
@@ -179,7 +182,7 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
                         C::RB - 1,
                         prev, out, s0, s1);
   pin_block<PREC, C::KS>(out, C::RB - 1, s0, s1);
-  return add_tail<PREC>(y, s0, s1, c0, c1);
+  return add_tail<PREC>(y, s0, s1, c0, c1, &t);
 }
 
 // Decode tile `tile` of a plan: exit depth, first permutation slot, count.
@@ -205,7 +208,8 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
                                          float* __restrict__ sdf, const int32_t* __restrict__ perm,
                                          int64_t start, int64_t cnt, int d, char* ring,
                                          const char* l1, int lane, int wave,
-                                         float* __restrict__ y_all) {
+                                         float* __restrict__ y_all, float dyn_r,
+                                         uint8_t* __restrict__ depth_out) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
@@ -258,15 +262,36 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
     wait_chunk();
     __syncthreads();
   }
-  for (int j = 2; j <= d; j += 2) {
-    y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actA, actB, M.c0[j - 1],
-                               M.c1[j - 1]);
+  // Map-free early exit (dyn_r > 0): a point's output is frozen after the
+  // first layer j >= 2 whose tail t_j is below dyn_r in magnitude; the
+  // workgroup stops once none of its points is still running.
+  bool alive = ok;
+  int dexit = d;
+  auto after_layer = [&](int j, float yn, float t) {
+    if (dyn_r > 0.0f) {
+      if (alive) {
+        y = yn;
+        if (fabsf(t) < dyn_r) {
+          alive = false;
+          dexit = j;
+        }
+      }
+      return __syncthreads_or(alive ? 1 : 0) != 0;
+    }
+    y = yn;
     if (yrow) yrow[j - 1] = y;
-    if (j + 1 > d) break;
-    y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, M.c0[j],
-                               M.c1[j]);
-    if (yrow) yrow[j] = y;
+    return true;
+  };
+  for (int j = 2; j <= d; j += 2) {
+    float t;
+    float yn = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actA, actB,
+                                      M.c0[j - 1], M.c1[j - 1], t);
+    if (!after_layer(j, yn, t) || j + 1 > d) break;
+    yn = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, M.c0[j],
+                                M.c1[j], t);
+    if (!after_layer(j + 1, yn, t)) break;
   }
+  if (depth_out && g == 0 && ok) depth_out[gi] = (uint8_t)(dyn_r > 0.0f ? dexit : d);
   // the last epilogue read a ring slot the next tile's first load may reuse
   if (nc > 0) __syncthreads();
   if (g == 0 && ok) sdf[gi] = y;
@@ -299,7 +324,8 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
       start = tile * Q;
       cnt = a.n - start < Q ? a.n - start : Q;
     }
-    run_tile<PREC, WP>(a.m, a.xyz, a.sdf, a.perm, start, cnt, d, ring, l1, lane, wave, a.y_all);
+    run_tile<PREC, WP>(a.m, a.xyz, a.sdf, a.perm, start, cnt, d, ring, l1, lane, wave, a.y_all,
+                       a.dyn_r, a.depth_out);
   }
 }
 
@@ -333,7 +359,8 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp_batch(BatchArgs a)
     int d;
     int64_t start, cnt;
     decode_tile<Q>(&q.plan, q.L, tile - q.tile0, d, start, cnt);
-    run_tile<PREC, WP>(M, q.xyz, q.sdf, q.perm, start, cnt, d, ring, l1, lane, wave, nullptr);
+    run_tile<PREC, WP>(M, q.xyz, q.sdf, q.perm, start, cnt, d, ring, l1, lane, wave, nullptr,
+                       0.0f, nullptr);
   }
 }
 

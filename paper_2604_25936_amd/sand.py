@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libsand.so")
 
 OK, ERR_INVALID, ERR_FORMAT, ERR_NOMEM, ERR_DEVICE, ERR_BUDGET, ERR_UNSUPPORTED, ERR_TIMEOUT = range(8)
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
-MODES = {"adaptive": 0, "full": 1, "forced": 2}
+MODES = {"adaptive": 0, "full": 1, "forced": 2, "dynamic": 3}
 
 
 class SandError(RuntimeError):
@@ -27,7 +27,7 @@ class SandError(RuntimeError):
 
 class QueryOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("max_depth", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_depth", ctypes.c_int32), ("dynamic_r", ctypes.c_float),
                 ("forced_depth", ctypes.c_void_p), ("depth_out", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
@@ -221,9 +221,10 @@ def query_grad_workspace_size(model, n, precision="fp32"):
     return int(library().sand_query_grad_workspace_size(model.handle, int(n), p))
 
 
-def _opts(precision, mode, max_depth, forced_depth, depth_out, workspace):
+def _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r=0.0):
     o = QueryOpts()
     library().sand_query_opts_init(ctypes.byref(o))
+    o.dynamic_r = float(dynamic_r)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.max_depth = int(max_depth)
@@ -244,21 +245,22 @@ def _check_points(xyz):
 
 
 def query(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_depth=0,
-          forced_depth=None, depth_out=None, workspace=None, stream=None):
-    """Signed distances of points ``xyz`` (float32 [n, 3] on the model's GPU)."""
+          forced_depth=None, depth_out=None, workspace=None, stream=None, dynamic_r=0.0):
+    """Signed distances of points ``xyz`` (float32 [n, 3] on the model's GPU).
+    mode "dynamic" needs no map and takes the residual threshold dynamic_r."""
     import torch
     _check_points(xyz)
     n = xyz.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xyz.device)
-    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r)
     _check(library().sand_query(model.handle, None if dmap is None else dmap.handle, _ptr(xyz), n,
                                 _ptr(out), ctypes.byref(o), _stream(stream)))
     return out
 
 
 def query_timed(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_depth=0,
-                forced_depth=None, depth_out=None, workspace=None, stream=None):
+                forced_depth=None, depth_out=None, workspace=None, stream=None, dynamic_r=0.0):
     """query() that waits and returns (out, phase_ms): device milliseconds of
     [lookup, scan, scatter, t-mlp, whole query] measured with HIP events."""
     import torch
@@ -266,7 +268,7 @@ def query_timed(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", m
     n = xyz.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xyz.device)
-    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r)
     ms = (ctypes.c_float * 5)()
     _check(library().sand_query_timed(model.handle, None if dmap is None else dmap.handle,
                                       _ptr(xyz), n, _ptr(out), ctypes.byref(o), _stream(stream),
