@@ -15,6 +15,8 @@ Modules:
               Eq. 5-7): required depth per point, sub-cell samples,
               max-pooling per voxel, far voxels
   dynamic  -- map-free early exit on small residuals (Sec. 4.4 ablation)
+  octree   -- the sparse network-depth octree: top-down subdivision, leaf
+              depths and far values, point lookup (Sec. 3.2, Eq. 5-7)
 
 Parity status per function (what pins it) is listed in each module header.
 """
@@ -22,8 +24,8 @@ Parity status per function (what pins it) is listed in each module header.
 from .blob import parse_blob
 from .tmlp import (voxel_index, lookup_depth, forward, forward_all_tails,
                    gradient, MODE_ADAPTIVE, MODE_FULL, MODE_FORCED)
-from . import depthmap, dynamic
+from . import depthmap, dynamic, octree
 
 __all__ = ["parse_blob", "voxel_index", "lookup_depth", "forward",
            "forward_all_tails", "gradient", "MODE_ADAPTIVE", "MODE_FULL",
-           "MODE_FORCED", "depthmap", "dynamic"]
+           "MODE_FORCED", "depthmap", "dynamic", "octree"]

@@ -16,6 +16,7 @@ import torch
 import oracle
 import oracle.depthmap as D
 import oracle.dynamic as DY
+import oracle.octree as OT
 import oracle.scalar
 import oracle.tmlp as T
 import synth
@@ -478,6 +479,121 @@ def check_dynamic_scalar_twin(seed=59, L=4, W=8, r=0.3):
         assert d[i] == dynamic_exit_loop(tr, r), f"point {i}"
 
 
+# -- sparse network-depth octree (Sec. 3.2, Eq. 5-7) -------------------------
+
+def constant_model(c, L=3, W=8, seed=61):
+    """y_i = c for every i: tail 1 is the constant c, later tails vanish."""
+    m = tiny_model(seed, L, W)
+    tl = [("linear", np.zeros(W), float(c))]
+    for t in m["tails"][1:]:
+        tl.append(("mult", np.zeros(W), 0.0, np.zeros(W), 0.0))
+    return dict(m, tails=tl)
+
+
+def _brute_tree(model, D, s, r):
+    """Top-down recursion with the scalar twin, pure Python."""
+    L = model["L"]
+    internal = [set() for _ in range(D)]
+    leaves = {}
+
+    def yl(p):
+        return oracle.scalar.forward_point(model, p, L)
+
+    def visit(l, ijk):
+        side = 2.0 / (1 << l)
+        c = [-1.0 + (v + 0.5) * side for v in ijk]
+        y = yl(c)
+        hit = abs(y) <= math.sqrt(3.0) * 2.0 ** (-l)
+        assert abs(abs(y) - math.sqrt(3.0) * 2.0 ** (-l)) > 1e-9, "centre on the test boundary"
+        if hit and l < D:
+            internal[l].add(ijk)
+            for a in (0, 1):
+                for b in (0, 1):
+                    for e in (0, 1):
+                        visit(l + 1, (2 * ijk[0] + a, 2 * ijk[1] + b, 2 * ijk[2] + e))
+        elif hit:
+            best = 0
+            for ka in range(s):
+                for kb in range(s):
+                    for kc in range(s):
+                        p = [-1.0 + side * (ijk[ax] + (kk + 0.5) / s)
+                             for ax, kk in enumerate((ka, kb, kc))]
+                        ys = [oracle.scalar.forward_point(model, p, j) for j in range(1, L + 1)]
+                        best = max(best, required_depth_loop(ys, r))
+            leaves[(l,) + ijk] = (best, 0.0)
+        else:
+            leaves[(l,) + ijk] = (0, y)
+
+    visit(0, (0, 0, 0))
+    return internal, leaves
+
+
+def check_octree_brute_force(seed=63, L=3, W=10, D=3, s=2, r=0.3):
+    model = tiny_model(seed, L, W)
+    tree = OT.build(model, D, s, r)
+    internal, leaves = _brute_tree(model, D, s, r)
+    for l in range(D):
+        assert tree["internal"][l] == internal[l], f"internal nodes differ at level {l}"
+    assert set(tree["leaves"]) == set(leaves), "leaf sets differ"
+    for k, (d, v) in leaves.items():
+        dd, vv = tree["leaves"][k]
+        assert dd == d and abs(vv - v) < 1e-12, f"leaf {k}: {tree['leaves'][k]} vs {(d, v)}"
+    assert sum(1 for k, (d, _) in leaves.items() if d > 0) > 0, "case should have near leaves"
+    assert len({k[0] for k in leaves}) > 1, "case should have leaves on several levels"
+
+
+def check_octree_constant_models(D=3):
+    t = OT.build(constant_model(2.0), D, 1, 1e-3)
+    assert t["leaves"] == {(0, 0, 0, 0): (0, 2.0)} and not t["internal"][0]
+    d, v, lv = OT.lookup(t, np.array([[0.1, -0.7, 0.99]]))
+    assert (d[0], v[0], lv[0]) == (0, 2.0, 0)
+    t = OT.build(constant_model(0.0), D, 2, 1e-3)
+    assert len(t["leaves"]) == 8 ** D and all(k[0] == D and dv == (1, 0.0)
+                                              for k, dv in t["leaves"].items())
+    t = OT.build(constant_model(0.3), D, 1, 1e-3)          # h = 1.73, .87, .43 > .3 > .22
+    assert len(t["leaves"]) == 8 ** 3 and all(k[0] == 3 and dv == (0, 0.3)
+                                              for k, dv in t["leaves"].items())
+    c = OT.SQRT3 * 0.25                                    # |y| = h exactly at level 2
+    t = OT.build(constant_model(c), D, 1, 1e-3)
+    assert len(t["internal"][2]) == 64 and all(k[0] == 3 for k in t["leaves"]), \
+        "a centre exactly half a diagonal away intersects"
+
+
+def check_octree_invariants(seed=65, L=3, W=10, D=4, s=1, r=0.3):
+    model = tiny_model(seed, L, W)
+    t = OT.build(model, D, s, r)
+    vol = sum(8 ** (D - k[0]) for k in t["leaves"])
+    assert vol == 8 ** D, "leaves must tile the cube exactly"
+    for (l, i, j, k), (d, v) in t["leaves"].items():
+        if l > 0:
+            assert (i // 2, j // 2, k // 2) in t["internal"][l - 1], "a leaf's parent is internal"
+        c = OT.centres(l, [[i, j, k]])
+        y = OT.y_last(model, c)[0]
+        if d > 0:
+            assert l == D and abs(y) <= OT.SQRT3 * 2.0 ** (-l), "near leaves sit at level D"
+        else:
+            assert abs(v - y) < 1e-12, "far leaves store y_L at their centre"
+            assert l == D or abs(y) > OT.SQRT3 * 2.0 ** (-l), "a far leaf above D misses the shape"
+    for l in range(D):
+        for ijk in t["internal"][l]:
+            y = OT.y_last(model, OT.centres(l, [ijk]))[0]
+            assert abs(y) <= OT.SQRT3 * 2.0 ** (-l)
+
+
+def check_octree_lookup(seed=67, L=3, W=10, D=4, n=400):
+    model = tiny_model(seed, L, W)
+    t = OT.build(model, D, 1, 0.3)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.concatenate([rng.uniform(-1, 1, size=(n, 3)), edge_coordinates(1 << D)[:60, None]
+                        * np.ones((1, 3))])
+    d, v, lv = OT.lookup(t, x)
+    for q in range(x.shape[0]):
+        l = int(lv[q])
+        ijk = tuple(T.voxel_index(x[q:q + 1], 1 << l)[0]) if l > 0 else (0, 0, 0)
+        assert (l,) + tuple(int(a) for a in ijk) in t["leaves"], f"point {q}: not its leaf"
+        assert t["leaves"][(l,) + tuple(int(a) for a in ijk)] == (d[q], v[q])
+
+
 ALL_CHECKS = [
     lambda: [check_cell_rule(R) for R in (2, 4, 32, 128)],
     check_textbook_mlp, check_quadratic_form, check_truncation,
@@ -488,4 +604,6 @@ ALL_CHECKS = [
     check_construct_brute_force,
     check_dynamic_definition, check_dynamic_hand_cases, check_dynamic_monotone_and_tails,
     check_dynamic_vanishing_tails, check_dynamic_scalar_twin,
+    check_octree_brute_force, check_octree_constant_models, check_octree_invariants,
+    check_octree_lookup,
 ]

@@ -9,6 +9,7 @@ import pytest
 
 import oracle.depthmap as D
 import oracle.dynamic as DY
+import oracle.octree as OT
 import oracle.tmlp as T
 import oracle_pins as P
 
@@ -200,6 +201,64 @@ def _dyn_no_clamp(t, r, max_depth=0):
     return _ORIG_EXIT(t, r, 0)
 
 
+def _octree_variant(strict=False, half_side=False, corner=False, min_pool=False, extra_level=False):
+    """A copy of the octree builder with one plausible mistake."""
+    def build(model, Dmax, s, r):
+        internal = [set() for _ in range(Dmax + (1 if extra_level else 0))]
+        leaves = {}
+        def h(l):
+            return (2.0 ** (-l)) if half_side else OT.SQRT3 * 2.0 ** (-l)
+        def test(y, l):
+            return abs(y) < h(l) if strict else abs(y) <= h(l)
+        y0 = OT.y_last(model, OT.centres(0, [[0, 0, 0]]))[0]
+        if test(y0, 0) and Dmax > 0:
+            internal[0].add((0, 0, 0))
+        else:
+            leaves[(0, 0, 0, 0)] = (0, float(y0))
+        top = Dmax + (1 if extra_level else 0)
+        for l in range(1, top + 1):
+            parents = sorted(internal[l - 1])
+            if not parents:
+                break
+            kids = np.array([(2 * i + a, 2 * j + b, 2 * k + c) for (i, j, k) in parents
+                             for a in (0, 1) for b in (0, 1) for c in (0, 1)], dtype=np.int64)
+            pts = OT.centres(l, kids) - (1.0 / (1 << l) if corner else 0.0)
+            y = OT.y_last(model, pts)
+            near = []
+            for kid, yy in zip(map(tuple, kids), y):
+                hit = test(yy, l)
+                if hit and l < top:
+                    internal[l].add(kid)
+                elif hit:
+                    near.append(kid)
+                else:
+                    leaves[(l,) + kid] = (0, float(yy))
+            if near:
+                R = 1 << l
+                vox = np.array([(i * R + j) * R + k for (i, j, k) in near], dtype=np.int64)
+                yall = T.forward_all_tails(model, D_sample(R, vox, s))
+                d = _REQUIRED(yall, r).reshape(len(near), s ** 3)
+                d = d.min(axis=1) if min_pool else d.max(axis=1)
+                for kid, dd in zip(near, d):
+                    leaves[(l,) + kid] = (int(dd), 0.0)
+        return {"D": top, "internal": internal, "leaves": leaves}
+    return build
+
+
+def D_sample(R, vox, s):
+    return _SAMPLES(R, vox, s)
+
+
+_REQUIRED = D.required_depth
+_SAMPLES = D.sample_points
+
+
+def _lookup_xz_swapped(tree, xyz):
+    x = np.asarray(xyz, dtype=np.float64)[:, ::-1].copy()
+    return _ORIG_LOOKUP(tree, x)
+
+
+_ORIG_LOOKUP = OT.lookup
 _ORIG_EXIT = DY.exit_from_tails
 _ORIG_REQUIRED = D.required_depth
 _ORIG_SAMPLES = D.sample_points
@@ -228,6 +287,12 @@ MUTANTS = {
     "dynamic test on outputs": (DY, "tails", _dyn_on_outputs),
     "dynamic residual sign kept": (DY, "exit_from_tails", _dyn_signed),
     "dynamic ignores max_depth": (DY, "exit_from_tails", _dyn_no_clamp),
+    "octree strict intersection test": (OT, "build", _octree_variant(strict=True)),
+    "octree half side for half diagonal": (OT, "build", _octree_variant(half_side=True)),
+    "octree far value at the corner": (OT, "build", _octree_variant(corner=True)),
+    "octree min-pooling near leaves": (OT, "build", _octree_variant(min_pool=True)),
+    "octree subdivides past D": (OT, "build", _octree_variant(extra_level=True)),
+    "octree lookup axes swapped": (OT, "lookup", _lookup_xz_swapped),
 }
 
 

@@ -92,3 +92,21 @@ def test_dynamic_exit_after_last_live_tail():
 
 def test_dynamic_matches_scalar_twin():
     P.check_dynamic_scalar_twin()
+
+
+# sparse network-depth octree (Sec. 3.2, Eq. 5-7)
+
+def test_octree_matches_recursive_scalar_twin():
+    P.check_octree_brute_force()
+
+
+def test_octree_closed_form_constant_models():
+    P.check_octree_constant_models()
+
+
+def test_octree_invariants():
+    P.check_octree_invariants()
+
+
+def test_octree_lookup_lands_in_containing_leaf():
+    P.check_octree_lookup()
