@@ -167,6 +167,42 @@ sand_status sand_construct_depthmap(sand_model model, const uint8_t* near_host,
                                     void* stream, sand_depthmap* out,
                                     uint8_t* depth_host, sand_map_info* info);
 
+/* What sand_construct_octree built. */
+typedef struct {
+  int32_t D;                   /* maximum depth */
+  int64_t internal_nodes[11];  /* subdivided nodes per level 0..D-1 */
+  int64_t leaves[11];          /* leaves per level 0..D */
+  int64_t near_leaves;         /* level-D leaves that meet the surface */
+  int64_t samples;             /* near_leaves * s^3 points run to full depth */
+  size_t bytes;                /* device memory of the octree */
+  int32_t depth_counts[17];    /* leaves per stored depth 0..16 */
+} sand_octree_info;
+
+/* Build the sparse network-depth octree of Sec. 3.2 from `model` on the GPU
+ * and return it as a map for sand_query (ADAPTIVE and FORCED), the
+ * gradient and the server.
+ *  D:  maximum depth, 1..10 (the paper uses 9: level-9 cells are the
+ *      512^3 grid's cells).
+ * Levels l = 0..D, node cells of side 2^(1-l) over [-1, 1]^3. From the root
+ * down, a node is subdivided when l < D and it meets the shape the network
+ * represents: |y_L(centre)| <= sqrt(3) 2^-l, its centre within half its
+ * diagonal (the paper's intersection test, Sec. 4.1, with the network's
+ * full-depth value as the distance; FP32 comparison). A level-D node that
+ * meets the shape is a near leaf storing the maximum of Eq. 5 over its s^3
+ * sub-cell centres (threshold r; s in {1, 2, 4, 8}); every other leaf is
+ * far: depth 0 and y_L at its centre (Eq. 7). Storage is pointer-free:
+ * per level a bitmask of internal nodes in Morton order with popcount
+ * ranks, and per child slot of each internal node a depth byte and a far
+ * value (see sand_octree_info.bytes). A point is answered by the leaf whose
+ * cell contains it, with the dense map's exact cell rule at level D.
+ *  precision: arithmetic of the full-depth passes (FP32 recommended).
+ * Blocking: runs on `stream` and waits for it.
+ * Errors: SAND_ERR_INVALID (null pointers, bad D, s, r or precision),
+ * SAND_ERR_NOMEM / SAND_ERR_DEVICE. */
+sand_status sand_construct_octree(sand_model model, int32_t D, int32_t s, float r,
+                                  int32_t precision, void* stream, sand_depthmap* out,
+                                  sand_octree_info* info);
+
 /* ---- queries ------------------------------------------------------------- */
 
 /* Bytes of device scratch a query of n points needs (same for the gradient). */

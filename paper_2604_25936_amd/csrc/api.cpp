@@ -503,8 +503,10 @@ extern "C" sand_status sand_build_depthmap(sand_model m, const uint8_t* depth_ho
 extern "C" void sand_free_depthmap(sand_depthmap dm) {
   if (!dm) return;
   DeviceGuard guard(dm->device);
-  (void)hipFree(dm->depth);
+  if (dm->depth) (void)hipFree(dm->depth);
   if (dm->far) (void)hipFree(dm->far);
+  if (dm->oct) (void)hipFree(dm->oct);
+  for (void* p : dm->owned) (void)hipFree(p);
   delete dm;
 }
 
@@ -646,6 +648,239 @@ extern "C" sand_status sand_construct_depthmap(sand_model m, const uint8_t* near
   return SAND_OK;
 }
 
+// ---------------------------------------------------------------- octree --
+
+namespace {
+
+// Device arrays owned by an octree under construction; handed to the map
+// object on success, freed otherwise.
+struct Owned {
+  std::vector<void*> p;
+  size_t bytes = 0;
+  template <class T>
+  hipError_t get(T** out, size_t n_bytes, hipStream_t s, bool zero = false) {
+    *out = nullptr;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, n_bytes > 0 ? n_bytes : 1);
+    if (e != hipSuccess) return e;
+    p.push_back(q);
+    bytes += n_bytes;
+    if (zero) e = hipMemsetAsync(q, 0, n_bytes > 0 ? n_bytes : 1, s);
+    *out = (T*)q;
+    return e;
+  }
+  void release() {
+    for (void* q : p) (void)hipFree(q);
+    p.clear();
+  }
+};
+
+}  // namespace
+
+extern "C" sand_status sand_construct_octree(sand_model m, int32_t D, int32_t sps, float r,
+                                             int32_t precision, void* stream, sand_depthmap* out,
+                                             sand_octree_info* info) {
+  const char* who = "sand_construct_octree";
+  if (!m || !out) return fail(SAND_ERR_INVALID, "%s: null model or out", who);
+  *out = nullptr;
+  if (D < 1 || D > kMaxOctDepth)
+    return fail(SAND_ERR_INVALID, "%s: D=%d is not in 1..%d", who, D, kMaxOctDepth);
+  if (sps != 1 && sps != 2 && sps != 4 && sps != 8)
+    return fail(SAND_ERR_INVALID, "%s: s=%d is not 1, 2, 4 or 8", who, sps);
+  if (!(r > 0.0f) || !std::isfinite(r))
+    return fail(SAND_ERR_INVALID, "%s: threshold r must be finite and > 0", who);
+  if (precision < 0 || precision > 2) return fail(SAND_ERR_INVALID, "%s: precision %d", who, precision);
+  DeviceGuard guard(m->device);
+  if (!guard.ok) return fail(SAND_ERR_DEVICE, "%s: cannot select device", who);
+  hipStream_t st = (hipStream_t)stream;
+  const int L = m->L;
+  const int64_t chunk_max = kMapChunk;
+  Owned own;       // the octree's arrays
+  DevBufs tmp;     // scratch of the build
+  OctreeArgs oa{};
+  oa.D = D;
+  sand_octree_info inf{};
+  inf.D = D;
+  auto bail = [&](hipError_t e) {
+    (void)hipStreamSynchronize(st);
+    own.release();
+    return device_fail(e, who);
+  };
+
+  // scratch for the full-depth passes: points, final values, all outputs
+  float *xyz = nullptr, *ylast = nullptr, *yall = nullptr;
+  hipError_t e = tmp.get(&xyz, chunk_max * 12);
+  if (e == hipSuccess) e = tmp.get(&ylast, chunk_max * 4);
+  if (e == hipSuccess) e = tmp.get(&yall, chunk_max * L * 4);
+  int64_t* total_d = nullptr;
+  uint32_t* near_count_d = nullptr;
+  if (e == hipSuccess) e = tmp.get(&total_d, 8);
+  if (e == hipSuccess) e = tmp.get(&near_count_d, 4);
+  if (e != hipSuccess) return fail(SAND_ERR_NOMEM, "%s: build scratch", who);
+
+  QueryArgs qa{};
+  qa.m = m->args[precision];
+  qa.full_depth = L;
+  auto y_at = [&](const float* pts, float* yout, int64_t n) {
+    qa.xyz = pts;
+    qa.sdf = yout;
+    qa.n = n;
+    return launch_tmlp(precision, qa, m->num_cu, st);
+  };
+
+  // level 0: the root
+  const float root_c[3] = {0.0f, 0.0f, 0.0f};
+  float y0 = 0.0f;
+  e = hipMemcpyAsync(xyz, root_c, 12, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = y_at(xyz, ylast, 1);
+  if (e == hipSuccess) e = hipMemcpyAsync(&y0, ylast, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return bail(e);
+  const float h0 = (float)std::sqrt(3.0);
+  uint64_t* parents = nullptr;   // internal codes of the previous level, Morton order
+  int64_t np = 0;
+  if (std::fabs(y0) <= h0) {
+    uint64_t one = 1ull, zero64 = 0ull;
+    uint32_t rank0 = 0;
+    uint64_t* b0 = nullptr;
+    uint32_t* r0 = nullptr;
+    e = own.get(&b0, 8, st);
+    if (e == hipSuccess) e = own.get(&r0, 4, st);
+    if (e == hipSuccess) e = tmp.get(&parents, 8);
+    if (e == hipSuccess) e = hipMemcpyAsync(b0, &one, 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(r0, &rank0, 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(parents, &zero64, 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // host sources are on the stack
+    if (e != hipSuccess) return bail(e);
+    oa.bits[0] = b0;
+    oa.rank[0] = r0;
+    np = 1;
+    inf.internal_nodes[0] = 1;
+  } else {
+    oa.root_leaf = 1;
+    oa.root_value = y0;
+    inf.leaves[0] = 1;
+  }
+
+  int32_t* near_slots = nullptr;
+  int64_t nnear = 0, nslots_D = 0;
+  uint64_t* parents_D = nullptr;
+  uint8_t* depth_D = nullptr;
+  for (int l = 1; l <= D && np > 0; ++l) {
+    const int64_t nslots = 8 * np;
+    uint8_t* dep = nullptr;
+    float* val = nullptr;
+    uint64_t* bits = nullptr;
+    uint32_t* rank = nullptr;
+    const int64_t words = l < D ? (((int64_t)1 << (3 * l)) + 63) / 64 : 0;
+    e = own.get(&dep, nslots, st);
+    if (e == hipSuccess) e = own.get(&val, nslots * 4, st);
+    if (e == hipSuccess && l < D) e = own.get(&bits, words * 8, st, true);
+    if (e == hipSuccess && l < D) e = own.get(&rank, words * 4, st);
+    if (e == hipSuccess && l == D) e = tmp.get(&near_slots, nslots * 4);
+    if (e == hipSuccess) e = hipMemsetAsync(near_count_d, 0, 4, st);
+    if (e != hipSuccess) return bail(e);
+    oa.depth[l] = dep;
+    oa.value[l] = val;
+    const float h = (float)(std::sqrt(3.0) * std::ldexp(1.0, -l));
+    for (int64_t first = 0; e == hipSuccess && first < nslots; first += chunk_max) {
+      const int64_t k = nslots - first < chunk_max ? nslots - first : chunk_max;
+      e = launch_oct_centres(parents, first, k, l, xyz, st);
+      if (e == hipSuccess) e = y_at(xyz, ylast, k);
+      if (e == hipSuccess)
+        e = launch_oct_classify(parents, ylast, first, k, l, D, h, bits, dep, val, near_slots,
+                                near_count_d, st);
+    }
+    if (e != hipSuccess) return bail(e);
+    if (l < D) {
+      int64_t total = 0;
+      e = launch_oct_rank(bits, words, rank, total_d, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(&total, total_d, 8, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return bail(e);
+      oa.bits[l] = bits;
+      oa.rank[l] = rank;
+      inf.internal_nodes[l] = total;
+      inf.leaves[l] = nslots - total;
+      uint64_t* next = nullptr;
+      if (total > 0) {
+        e = tmp.get(&next, total * 8);
+        if (e == hipSuccess) e = launch_oct_list(bits, rank, words, next, st);
+        if (e != hipSuccess) return bail(e);
+      }
+      parents = next;
+      np = total;
+    } else {
+      uint32_t nn = 0;
+      e = hipMemcpyAsync(&nn, near_count_d, 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return bail(e);
+      nnear = nn;
+      nslots_D = nslots;
+      parents_D = parents;
+      depth_D = dep;
+      inf.leaves[l] = nslots;
+    }
+  }
+
+  // near leaves at level D: Eq. 5 over s^3 sub-cell samples, max-pooled (Eq. 6)
+  const int64_t s3 = (int64_t)sps * sps * sps, nsamp = nnear * s3;
+  if (nnear > 0) {
+    uint32_t* depth32 = nullptr;
+    e = tmp.get(&depth32, nslots_D * 4);
+    if (e == hipSuccess) e = hipMemsetAsync(depth32, 0, nslots_D * 4, st);
+    qa.y_all = yall;
+    for (int64_t first = 0; e == hipSuccess && first < nsamp; first += chunk_max) {
+      const int64_t k = nsamp - first < chunk_max ? nsamp - first : chunk_max;
+      e = launch_oct_samples(near_slots, parents_D, first, k, D, sps, xyz, st);
+      if (e == hipSuccess) e = y_at(xyz, ylast, k);
+      if (e == hipSuccess) e = launch_map_pool(yall, L, near_slots, first, k, sps, r, depth32, st);
+    }
+    qa.y_all = nullptr;
+    if (e == hipSuccess) e = launch_oct_finish(near_slots, nnear, depth32, depth_D, st);
+    if (e != hipSuccess) return bail(e);
+  }
+  inf.near_leaves = nnear;
+  inf.samples = nsamp;
+
+  // the descriptor
+  OctreeArgs* oa_d = nullptr;
+  e = hipMalloc((void**)&oa_d, sizeof(OctreeArgs));
+  if (e == hipSuccess) e = hipMemcpyAsync(oa_d, &oa, sizeof(OctreeArgs), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    if (oa_d) (void)hipFree(oa_d);
+    return bail(e);
+  }
+  inf.bytes = own.bytes + sizeof(OctreeArgs);
+  if (info) {
+    // leaves per stored depth: far leaves at every level, near leaves by depth
+    inf.depth_counts[0] = 0;
+    for (int l = 0; l <= D; ++l) inf.depth_counts[0] += (int32_t)inf.leaves[l];
+    inf.depth_counts[0] -= (int32_t)nnear;
+    if (nnear > 0) {
+      std::vector<uint8_t> dh((size_t)nslots_D);
+      e = hipMemcpy(dh.data(), depth_D, (size_t)nslots_D, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        (void)hipFree(oa_d);
+        return bail(e);
+      }
+      for (uint8_t v : dh)
+        if (v >= 1 && v <= 16) inf.depth_counts[v]++;
+    }
+    *info = inf;
+  }
+  sand_depthmap dm = new sand_depthmap_s();
+  dm->model = m;
+  dm->device = m->device;
+  dm->R = 1 << D;
+  dm->oct = oa_d;
+  dm->owned = own.p;
+  own.p.clear();
+  *out = dm;
+  return SAND_OK;
+}
+
 // --------------------------------------------------------------- queries --
 
 namespace sand {
@@ -710,10 +945,11 @@ sand_status run_bucketing(sand_model m, sand_depthmap dm, const float* xyz, int6
   Plan* plan = (Plan*)(ws + w.plan);
   const uint8_t* map = dm ? dm->depth : nullptr;
   const float* far = dm ? dm->far : nullptr;
+  const OctreeArgs* oct = dm ? dm->oct : nullptr;
   const int R = dm ? dm->R : 2;
   hipError_t e;
   mark(0);
-  if ((e = launch_lookup_count(xyz, n, map, R, far, o.forced_depth, o.mode, m->L, o.max_depth, depth,
+  if ((e = launch_lookup_count(xyz, n, map, R, far, oct, o.forced_depth, o.mode, m->L, o.max_depth, depth,
                                sdf, grad, counts, s)) != hipSuccess)
     return device_fail(e, "lookup launch");
   mark(1);

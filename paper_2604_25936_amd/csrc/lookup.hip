@@ -34,6 +34,41 @@ __device__ __forceinline__ int cell_index(float x, float s, int half) {
   return (int)floorf(v) + half;
 }
 
+// Leaf of the octree holding a point: its stored depth d and far value v.
+// The point's cell at level D follows from the exact cell rule; its cell at
+// every coarser level is that index shifted right. The descent follows
+// internal nodes from the root; a node's child slot is 8 rank(parent) +
+// child, rank counting the internal nodes before it at its level.
+__device__ __forceinline__ void octree_leaf(const OctreeArgs& o, float x, float y, float z,
+                                            int& d, float& v) {
+  if (o.root_leaf) {
+    d = 0;
+    v = o.root_value;
+    return;
+  }
+  const int D = o.D, half = 1 << (D - 1);
+  const float s = (float)half;
+  const int ix = cell_index(x, s, half), iy = cell_index(y, s, half), iz = cell_index(z, s, half);
+  uint64_t p = 0;   // code of the internal node at level l-1 holding the point
+  for (int l = 1; l <= D; ++l) {
+    const int sh = D - l;
+    const int child = (((ix >> sh) & 1) << 2) | (((iy >> sh) & 1) << 1) | ((iz >> sh) & 1);
+    const uint64_t w = o.bits[l - 1][p >> 6];
+    const uint64_t rk = o.rank[l - 1][p >> 6] + __popcll(w & ((1ull << (p & 63)) - 1ull));
+    const uint64_t slot = 8ull * rk + (uint64_t)child;
+    const uint64_t m = 8ull * p + (uint64_t)child;
+    if (l < D && ((o.bits[l][m >> 6] >> (m & 63)) & 1ull)) {
+      p = m;
+      continue;
+    }
+    d = o.depth[l][slot];
+    v = o.value[l][slot];
+    return;
+  }
+  d = 0;                      // not reached: level D has no internal nodes
+  v = __builtin_nanf("");
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = threadIdx.x & 63;
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -56,9 +91,10 @@ __device__ __forceinline__ void wave_histogram(int d, bool valid, int* hist) {
 // Body of one lookup block: points [blk*4096, blk*4096 + 4096) of one query.
 __device__ __forceinline__ void lookup_block(
     int64_t blk, const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
-    int R, const float* __restrict__ far, const uint8_t* __restrict__ forced,
-    int mode, int L, int max_depth, uint8_t* __restrict__ depth,
-    float* __restrict__ sdf, float* __restrict__ grad, int32_t* __restrict__ counts) {
+    int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
+    const uint8_t* __restrict__ forced, int mode, int L, int max_depth,
+    uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
+    int32_t* __restrict__ counts) {
   __shared__ float sx[3 * kLookupThreads];
   __shared__ int hist[kBuckets];
   const int t = threadIdx.x;
@@ -81,10 +117,15 @@ __device__ __forceinline__ void lookup_block(
     if (valid) {
       const float x = sx[3 * t], y = sx[3 * t + 1], z = sx[3 * t + 2];
       int cell = -1;
-      if (map != nullptr) {
+      float farv = __builtin_nanf("");
+      int od = 0;
+      if (oct != nullptr && mode != 1) {
+        octree_leaf(*oct, x, y, z, od, farv);
+      } else if (map != nullptr) {
         const int ix = cell_index(x, s, half), iy = cell_index(y, s, half),
                   iz = cell_index(z, s, half);
         cell = (ix * R + iy) * R + iz;
+        if (far != nullptr) farv = far[cell];
       }
       if (mode == 1) {
         d = L;
@@ -92,12 +133,12 @@ __device__ __forceinline__ void lookup_block(
         d = forced[q];
         if (d > L) d = L;
       } else {
-        d = map[cell];
+        d = oct != nullptr ? od : map[cell];
       }
       if (max_depth > 0 && d > max_depth) d = max_depth;
       depth[q] = (uint8_t)d;
       if (d == 0) {
-        if (sdf) sdf[q] = (far != nullptr && cell >= 0) ? far[cell] : __builtin_nanf("");
+        if (sdf) sdf[q] = farv;
         if (grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
       }
     }
@@ -109,11 +150,12 @@ __device__ __forceinline__ void lookup_block(
 
 __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
     const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
-    int R, const float* __restrict__ far, const uint8_t* __restrict__ forced,
-    int mode, int L, int max_depth, uint8_t* __restrict__ depth,
-    float* __restrict__ sdf, float* __restrict__ grad, int32_t* __restrict__ counts) {
-  lookup_block(blockIdx.x, xyz, n, map, R, far, forced, mode, L, max_depth, depth, sdf, grad,
-               counts);
+    int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
+    const uint8_t* __restrict__ forced, int mode, int L, int max_depth,
+    uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
+    int32_t* __restrict__ counts) {
+  lookup_block(blockIdx.x, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf,
+               grad, counts);
 }
 
 constexpr int kScanThreads = 256;
@@ -249,8 +291,8 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_batch(const BatchReq*
                                                                  int nreq, int max_depth) {
   const int r = find_request(reqs, nreq, blockIdx.x);
   const BatchReq& q = reqs[r];
-  lookup_block((int64_t)blockIdx.x - q.blk0, q.xyz, q.n, q.map, q.R, q.far, nullptr, 0, q.L,
-               max_depth, q.depth, q.sdf, nullptr, q.counts);
+  lookup_block((int64_t)blockIdx.x - q.blk0, q.xyz, q.n, q.map, q.R, q.far, q.oct, nullptr, 0,
+               q.L, max_depth, q.depth, q.sdf, nullptr, q.counts);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_batch(BatchReq* __restrict__ reqs,
@@ -287,12 +329,12 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
 }  // namespace
 
 hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map, int R,
-                               const float* far, const uint8_t* forced, int mode, int L,
-                               int max_depth, uint8_t* depth, float* sdf, float* grad,
-                               int32_t* counts, hipStream_t s) {
+                               const float* far, const OctreeArgs* oct, const uint8_t* forced,
+                               int mode, int L, int max_depth, uint8_t* depth, float* sdf,
+                               float* grad, int32_t* counts, hipStream_t s) {
   const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
   hipLaunchKernelGGL(k_lookup_count, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, xyz,
-                     n, map, R, far, forced, mode, L, max_depth, depth, sdf, grad, counts);
+                     n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad, counts);
   return hipGetLastError();
 }
 

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/sand.h"
 #include "sand_internal.h"
 
@@ -25,9 +27,11 @@ struct sand_model_s {
 struct sand_depthmap_s {
   sand_model model = nullptr;   // identity only: never dereferenced when freeing
   int device = 0;               // so the map can be freed after its model
-  int R = 0;
-  uint8_t* depth = nullptr;   // device [R^3]
-  float* far = nullptr;       // device [R^3] or null
+  int R = 0;                    // dense: R; octree: 2^D
+  uint8_t* depth = nullptr;   // device [R^3] (dense maps)
+  float* far = nullptr;       // device [R^3] or null (dense maps)
+  sand::OctreeArgs* oct = nullptr;   // device descriptor (octree maps)
+  std::vector<void*> owned;          // octree arrays
 };
 
 namespace sand {

@@ -62,6 +62,26 @@ struct ModelArgs {
   float c1[kMaxLayers];    // tail bias of the second factor (1 for linear)
 };
 
+// Sparse network-depth octree (Sec. 3.2), pointer-free. Node codes are
+// Morton codes (x, y, z bits interleaved, x most significant per level);
+// the children of internal node p are 8p + (a << 2 | b << 1 | c). Level l
+// (0..D-1) keeps a bitmask of its internal nodes over all 8^l codes and the
+// exclusive popcount prefix of each 64-bit word; child slot
+// 8 rank_l(p) + child of level l+1 holds that child's leaf payload:
+// depth 0 with the stored far value, 1..L for a near leaf (level D only),
+// 255 for an internal child.
+constexpr int kMaxOctDepth = 10;
+struct OctreeArgs {
+  int D;
+  int root_leaf;                            // 1: the root is the only leaf
+  float root_value;                         // its far value
+  int pad;
+  const uint64_t* bits[kMaxOctDepth];       // level l = 0..D-1
+  const uint32_t* rank[kMaxOctDepth];
+  const uint8_t* depth[kMaxOctDepth + 1];   // level l = 1..D, per child slot
+  const float* value[kMaxOctDepth + 1];
+};
+
 // Bucketed work plan written on the device by the scan kernel.
 struct Plan {
   int64_t start[kBuckets];      // first perm slot of depth bucket d
@@ -95,8 +115,9 @@ struct BatchReq {
   uint8_t* depth;          // [n] scratch
   int32_t* perm;           // [n] scratch
   int32_t* counts;         // [ceil(n/4096)][kBuckets] scratch
-  const uint8_t* map;      // R^3 depth map
+  const uint8_t* map;      // R^3 depth map, or null for an octree map
   const float* far;        // R^3 far values or null
+  const OctreeArgs* oct;   // octree map (device), or null
   const ModelArgs* model;  // device copy of the model's arguments
   int64_t n;
   int64_t blk0;            // first lookup block of this query in the launch
@@ -127,7 +148,8 @@ struct AdjointArgs {
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map,
-                               int R, const float* far, const uint8_t* forced,
+                               int R, const float* far, const OctreeArgs* oct,
+                               const uint8_t* forced,
                                int mode, int L, int max_depth, uint8_t* depth,
                                float* sdf, float* grad, int32_t* counts, hipStream_t s);
 hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q,
@@ -148,6 +170,22 @@ hipError_t launch_map_pool(const float* y_all, int L, const int32_t* list, int64
                            int64_t nsamp, int sps, float r, uint32_t* depth32, hipStream_t s);
 hipError_t launch_map_finish(const uint8_t* near, const float* center_sdf, const uint32_t* depth32,
                              int64_t cells, uint8_t* depth, float* far, hipStream_t s);
+
+// sparse octree construction (octree.hip)
+hipError_t launch_oct_centres(const uint64_t* parents, int64_t first, int64_t nslots, int level,
+                              float* xyz, hipStream_t s);
+hipError_t launch_oct_classify(const uint64_t* parents, const float* y, int64_t first,
+                               int64_t nslots, int level, int D, float h, uint64_t* bits,
+                               uint8_t* depth, float* value, int32_t* near_slots,
+                               uint32_t* near_count, hipStream_t s);
+hipError_t launch_oct_rank(const uint64_t* bits, int64_t words, uint32_t* rank, int64_t* total,
+                           hipStream_t s);
+hipError_t launch_oct_list(const uint64_t* bits, const uint32_t* rank, int64_t words,
+                           uint64_t* list, hipStream_t s);
+hipError_t launch_oct_samples(const int32_t* near_slots, const uint64_t* parents, int64_t first,
+                              int64_t nsamp, int D, int sps, float* xyz, hipStream_t s);
+hipError_t launch_oct_finish(const int32_t* near_slots, int64_t nnear, const uint32_t* depth32,
+                             uint8_t* depth, hipStream_t s);
 
 int tmlp_tile_points(int prec);
 size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L);

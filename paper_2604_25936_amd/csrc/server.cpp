@@ -187,6 +187,7 @@ void sand_server_s::launch(Slot* s) {
     d.counts = (int32_t*)(base + lay.counts);
     d.map = r->map->depth;
     d.far = r->map->far;
+    d.oct = r->map->oct;
     d.R = r->map->R;
     d.L = r->model->L;
     d.model = r->model->args_dev[prec];

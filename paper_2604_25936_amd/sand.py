@@ -51,6 +51,13 @@ class MapInfo(ctypes.Structure):
                 ("depth_counts", ctypes.c_int32 * 17)]
 
 
+class OctreeInfo(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("internal_nodes", ctypes.c_int64 * 11),
+                ("leaves", ctypes.c_int64 * 11), ("near_leaves", ctypes.c_int64),
+                ("samples", ctypes.c_int64), ("bytes", ctypes.c_size_t),
+                ("depth_counts", ctypes.c_int32 * 17)]
+
+
 _lib = None
 
 
@@ -72,6 +79,8 @@ def library():
             "sand_free_depthmap": (None, [P]),
             "sand_construct_depthmap": (I32, [P, P, P, I32, I32, ctypes.c_float, I32, P,
                                               ctypes.POINTER(P), P, ctypes.POINTER(MapInfo)]),
+            "sand_construct_octree": (I32, [P, I32, I32, ctypes.c_float, I32, P,
+                                            ctypes.POINTER(P), ctypes.POINTER(OctreeInfo)]),
             "sand_query_workspace_size": (SZ, [I64]),
             "sand_query_grad_workspace_size": (SZ, [P, I64, I32]),
             "sand_query": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P]),
@@ -185,6 +194,22 @@ def load_model(blob, device=0):
 
 def build_depthmap(model, depth, far=None):
     return DepthMap(model, depth, far)
+
+
+def construct_octree(model, D=9, s=1, r=1.5e-4, precision="fp32", stream=None):
+    """Build the sparse network-depth octree from the model on the GPU
+    (sand_construct_octree). Returns (DepthMap, info dict)."""
+    info = OctreeInfo()
+    h = ctypes.c_void_p()
+    p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(library().sand_construct_octree(model.handle, int(D), int(s), float(r), p,
+                                           _stream(stream), ctypes.byref(h), ctypes.byref(info)))
+    dm = DepthMap(model, 1 << int(D), _handle=h)
+    D = info.D
+    return dm, {"D": D, "internal_nodes": list(info.internal_nodes)[:D],
+                "leaves": list(info.leaves)[:D + 1], "near_leaves": info.near_leaves,
+                "samples": info.samples, "bytes": info.bytes,
+                "depth_counts": list(info.depth_counts)}
 
 
 def construct_depthmap(model, near, center_sdf, s=4, r=1.5e-4, precision="fp32", stream=None):

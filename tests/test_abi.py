@@ -92,6 +92,9 @@ def test_null_arguments():
     info = sand.MapInfo()
     assert lib.sand_construct_depthmap(None, None, None, 4, 2, 1e-3, 0, None, ctypes.byref(h),
                                        None, ctypes.byref(info)) == sand.ERR_INVALID
+    oinfo = sand.OctreeInfo()
+    assert lib.sand_construct_octree(None, 5, 1, 1e-3, 0, None, ctypes.byref(h),
+                                     ctypes.byref(oinfo)) == sand.ERR_INVALID
 
 
 def test_workspace_size():
