@@ -236,7 +236,7 @@ def gen_inputs(legs, n_models):
     return out
 
 
-def mapbuild_leg(sand, torch, model, prims, R=128, s=4, r=1.5e-4, reps=3):
+def mapbuild_leg(sand, torch, model, prims, xyz, R=128, s=4, r=1.5e-4, reps=3):
     """Building the 128^3 network-depth map from the 8x256 model (Sec. 3.2,
     Eq. 5-7): near-surface voxels by the centre / half-diagonal test against
     the analytic scene, 4^3 sub-cell samples each (the 512^3 grid points in
@@ -254,10 +254,52 @@ def mapbuild_leg(sand, torch, model, prims, R=128, s=4, r=1.5e-4, reps=3):
         ts.append(time.perf_counter() - t0)
         dm.free()
     t = float(np.median(ts))
+    # the 512^3 grid through the map built this way: far voxels return their
+    # stored centre value without running the network (Eq. 7)
+    dm, depth, info = sand.construct_depthmap(model, near, csdf, s=s, r=r, precision="fp32")
+    out = torch.empty(xyz.shape[0], dtype=torch.float32, device=xyz.device)
+    q = {}
+    for prec in ("bf16", "fp32"):
+        tq = time_steps(lambda p=prec: sand.query(model, dm, xyz, out=out, precision=p), 3, 1)
+        q[prec] = {"queries_per_s": xyz.shape[0] / tq, "ms_per_step": tq * 1e3}
+    dm.free()
     return {"R": R, "samples_per_axis": s, "r": r, "near_voxels": info["near_voxels"],
             "samples": info["samples"], "ms": t * 1e3, "samples_per_s": info["samples"] / t,
             "depth_counts": info["depth_counts"][:L + 1],
-            "note": "host-inclusive: mask/centre upload, all kernels, map read-back"}
+            "note": "host-inclusive: mask/centre upload, all kernels, map read-back",
+            "query_512grid_with_this_map": q}
+
+
+def octree_leg(sand, torch, model, xyz, D=9, s=1, r=1.5e-4, reps=3):
+    """The paper's own pipeline on this model: build the sparse network-depth
+    octree (max depth 9: level-9 leaves are the 512^3 grid's cells, one
+    sample each, r = 1.5e-4, FP32), then query the 512^3 grid through it
+    (far leaves answer from their stored value)."""
+    import numpy as np
+    sand.construct_octree(model, D=D, s=s, r=r)            # warm-up
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dm, info = sand.construct_octree(model, D=D, s=s, r=r)
+        ts.append(time.perf_counter() - t0)
+        dm.free()
+    dm, info = sand.construct_octree(model, D=D, s=s, r=r)
+    n = xyz.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    depth = torch.empty(n, dtype=torch.uint8, device=xyz.device)
+    q = {}
+    for prec in ("bf16", "fp32"):
+        t = time_steps(lambda p=prec: sand.query(model, dm, xyz, out=out, precision=p,
+                                                 depth_out=depth), 3, 1)
+        q[prec] = {"queries_per_s": n / t, "ms_per_step": t * 1e3}
+    hist = torch.bincount(depth.to(torch.int64), minlength=L + 1).cpu().numpy()
+    dm.free()
+    return {"D": D, "samples_per_axis": s, "r": r, "build_ms": float(np.median(ts)) * 1e3,
+            "internal_nodes": info["internal_nodes"], "leaves": info["leaves"],
+            "near_leaves": info["near_leaves"], "bytes": info["bytes"],
+            "query_512grid": q, "query_exit_histogram": [int(c) for c in hist],
+            "note": "build is host-inclusive (one host round trip per level)"}
 
 
 def percentile(v, q):
@@ -405,7 +447,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--legs", default="all",
-                    help="'all', or a comma list of headline,compare,c3,grad,serving,mapbuild,cpu")
+                    help="'all', or a comma list of headline,compare,c3,grad,serving,mapbuild,"
+                         "octree,cpu")
     ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--serving-models", type=int, default=64)
     ap.add_argument("--headline-mode", default="adaptive", choices=["adaptive", "full"],
@@ -418,7 +461,7 @@ def main():
               "shards by splitting the point set, with no exchange, and is not run on several "
               "GPUs here.", file=sys.stderr)
         sys.exit(2)
-    legs = {"headline", "compare", "c3", "grad", "serving", "mapbuild", "cpu"} \
+    legs = {"headline", "compare", "c3", "grad", "serving", "mapbuild", "octree", "cpu"} \
         if args.legs == "all" else \
         set(args.legs.split(",")) | {"headline"}
 
@@ -557,7 +600,10 @@ def main():
     if "mapbuild" in legs:
         log("map construction leg: 128^3 map from the 8x256 model, 4^3 samples per near voxel")
         secondary("mapbuild", lambda: mapbuild_leg(sand, torch, model,
-                                                   synth.random_primitives(SURFACE_SEED)))
+                                                   synth.random_primitives(SURFACE_SEED), xyz))
+    if "octree" in legs:
+        log("octree leg: max-depth-9 network-depth octree from the 8x256 model, 512^3 queries")
+        secondary("octree", lambda: octree_leg(sand, torch, model, xyz))
     if "serving" in legs:
         log(f"serving leg: {args.serving_models} resident models")
         secondary("serving", lambda: serving_leg(sand, torch, inputs, args.serving_models))
