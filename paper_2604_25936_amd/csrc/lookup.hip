@@ -117,15 +117,14 @@ __device__ __forceinline__ void lookup_block(
     if (valid) {
       const float x = sx[3 * t], y = sx[3 * t + 1], z = sx[3 * t + 2];
       int cell = -1;
-      float farv = __builtin_nanf("");
+      float farv = __builtin_nanf("");   // octree: the leaf's value; dense: read below
       int od = 0;
-      if (oct != nullptr && mode != 1) {
-        octree_leaf(*oct, x, y, z, od, farv);
+      if (oct != nullptr) {
+        if (mode != 1) octree_leaf(*oct, x, y, z, od, farv);
       } else if (map != nullptr) {
         const int ix = cell_index(x, s, half), iy = cell_index(y, s, half),
                   iz = cell_index(z, s, half);
         cell = (ix * R + iy) * R + iz;
-        if (far != nullptr) farv = far[cell];
       }
       if (mode == 1) {
         d = L;
@@ -138,6 +137,7 @@ __device__ __forceinline__ void lookup_block(
       if (max_depth > 0 && d > max_depth) d = max_depth;
       depth[q] = (uint8_t)d;
       if (d == 0) {
+        if (oct == nullptr && far != nullptr && cell >= 0) farv = far[cell];
         if (sdf) sdf[q] = farv;
         if (grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
       }
