@@ -66,7 +66,9 @@ __device__ __forceinline__ void tail_fma16(float& s0, float& s1, float w0, float
 }
 
 // Epilogue of one output block: sine, tail partial sums, pack for the next layer.
-template <int PREC, int KS>
+// PACK = false: the layer is the tile's last, so its activations are not
+// converted for a next layer.
+template <int PREC, int KS, bool PACK = true>
 __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int rb,
                                          const typename Tr<PREC>::Acc& acc,
                                          typename Tr<PREC>::V (&out)[KS], float& s0, float& s1) {
@@ -78,8 +80,10 @@ __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int
 #pragma unroll
     for (int e = 0; e < 16; ++e) h[e] = sin_rev(acc[e]);
     tail_fma16(s0, s1, w0, w1, h);
+    if constexpr (PACK) {
 #pragma unroll
-    for (int e = 0; e < 16; ++e) T::template put<KS>(out, rb, e, h[e]);
+      for (int e = 0; e < 16; ++e) T::template put<KS>(out, rb, e, h[e]);
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < T::NR / 4; ++i) {
@@ -91,7 +95,7 @@ __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int
         const float v = sin_rev(acc[e]);
         s0 = fmaf(ta[k], v, s0);
         s1 = fmaf(tb[k], v, s1);
-        T::template put<KS>(out, rb, e, v);
+        if constexpr (PACK) T::template put<KS>(out, rb, e, v);
       }
     }
   }
@@ -101,12 +105,14 @@ __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int
 // may sink it past the following barriers and keep every block's
 // accumulators and tail weights live at once (spilling to scratch). An
 // empty asm that reads the block's results pins the epilogue in place.
-template <int PREC, int KS>
+template <int PREC, int KS, bool PACK = true>
 __device__ __forceinline__ void pin_block(const typename Tr<PREC>::V (&out)[KS], int rb, float s0,
                                           float s1) {
   using T = Tr<PREC>;
   asm volatile("" ::"v"(s0), "v"(s1));
-  if constexpr (T::VB == 16) {
+  if constexpr (!PACK) {
+    return;
+  } else if constexpr (T::VB == 16) {
     asm volatile("" ::"v"(out[2 * rb]), "v"(out[2 * rb + 1]));
   } else {
 #pragma unroll
@@ -185,54 +191,14 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
   return add_tail<PREC>(y, s0, s1, c0, c1, &t);
 }
 
-// Decode tile `tile` of a plan: exit depth, first permutation slot, count.
-template <int Q>
-__device__ __forceinline__ void decode_tile(const Plan* plan, int L, int64_t tile, int& d,
-                                            int64_t& start, int64_t& cnt) {
-  d = 1;
-  for (int dd = L; dd >= 1; --dd)
-    if (tile < plan->tile_end[dd]) {
-      d = dd;
-      break;
-    }
-  const int64_t local = tile - plan->tile_end[d + 1];
-  start = plan->start[d] + local * Q;
-  cnt = plan->count[d] - local * Q;
-  if (cnt > Q) cnt = Q;
-}
-
-// Evaluate one tile: cnt points of exit depth d, the i-th being point
-// perm[start + i] (or start + i without a permutation).
-template <int PREC, int WP>
-__device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __restrict__ xyz,
-                                         float* __restrict__ sdf, const int32_t* __restrict__ perm,
-                                         int64_t start, int64_t cnt, int d, char* ring,
-                                         const char* l1, int lane, int wave,
-                                         float* __restrict__ y_all, float dyn_r,
-                                         uint8_t* __restrict__ depth_out) {
+// Layer 1 and the partial sums of its tail, pipelined like the hidden
+// layers: the MFMAs of block rb go with the epilogue of block rb-1.
+template <int PREC, int WP, bool PACK>
+__device__ __forceinline__ void layer1(const char* l1, int lane, int g, float px, float py,
+                                       float pz, typename Tr<PREC>::V (&act)[Cfg<PREC, WP>::KS],
+                                       float& s0, float& s1) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
-  using V = typename T::V;
-  const int g = T::grp(lane), col = T::col(lane);
-  const char* hidden = M.chunks + C::L1B;
-
-  // This wavefront's point; every lane of the same column holds it.
-  const int qi = wave * T::NQ + col;
-  const bool ok = qi < cnt;
-  int64_t gi = 0;
-  float px = 0.0f, py = 0.0f, pz = 0.0f;
-  if (ok) {
-    gi = perm ? (int64_t)perm[start + qi] : start + qi;
-    const float* p = xyz + 3 * gi;
-    px = p[0];
-    py = p[1];
-    pz = p[2];
-  }
-
-  V actA[C::KS], actB[C::KS];
-  float s0 = 0.0f, s1 = 0.0f;
-  // layer 1, pipelined like the hidden layers: MFMAs of block rb with the
-  // epilogue of block rb-1
   typename T::Acc prev = {};
 #pragma unroll
   for (int rb = 0; rb <= C::RB; ++rb) {
@@ -244,21 +210,64 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, const float* __rest
         acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
     }
     if (rb > 0) {
-      epilogue<PREC, C::KS>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1, prev, actA, s0,
-                            s1);
-      pin_block<PREC, C::KS>(actA, rb - 1, s0, s1);
+      epilogue<PREC, C::KS, PACK>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1, prev,
+                                  act, s0, s1);
+      pin_block<PREC, C::KS, PACK>(act, rb - 1, s0, s1);
     }
     prev = acc;
   }
+}
+
+// Decode tile `tile` of a plan: exit depth, first permutation slot, count.
+// tile_end[dd] falls as dd grows and is 0 beyond the deepest depth, so the
+// depth is the number of dd >= 1 with tile < tile_end[dd]: independent
+// reads, no dependent search.
+template <int Q>
+__device__ __forceinline__ void decode_tile(const Plan* plan, int L, int64_t tile, int& d,
+                                            int64_t& start, int64_t& cnt) {
+  d = 0;
+#pragma unroll
+  for (int dd = 1; dd < kBuckets; ++dd) d += (int)(tile < plan->tile_end[dd]);
+  if (d < 1) d = 1;
+  const int64_t local = tile - plan->tile_end[d + 1];
+  start = plan->start[d] + local * Q;
+  cnt = plan->count[d] - local * Q;
+  if (cnt > Q) cnt = Q;
+}
+
+// Evaluate one tile of exit depth d. This lane's point is gi (< 0: none)
+// at (px, py, pz); every lane of the same column holds the same point.
+template <int PREC, int WP>
+__device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__ sdf, int d,
+                                         int gi, float px, float py, float pz, char* ring,
+                                         const char* l1, int lane, int wave,
+                                         float* __restrict__ y_all, float dyn_r,
+                                         uint8_t* __restrict__ depth_out) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  const int g = T::grp(lane);
+  const char* hidden = M.chunks + C::L1B;
+  const bool ok = gi >= 0;
+
+  // The first hidden chunk streams into the ring while layer 1 runs (layer 1
+  // reads only its own LDS region; every ring slot is free at a tile's start).
+  const int nc = (d - 1) * C::RB;
+  if (nc > 0) load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
+
+  V actA[C::KS], actB[C::KS];
+  float s0 = 0.0f, s1 = 0.0f;
+  if (d > 1)
+    layer1<PREC, WP, true>(l1, lane, g, px, py, pz, actA, s0, s1);
+  else
+    layer1<PREC, WP, false>(l1, lane, g, px, py, pz, actA, s0, s1);
   float y = add_tail<PREC>(0.0f, s0, s1, M.c0[0], M.c1[0]);
   // every accumulated output y_j, for building a depth map (Eq. 5)
-  float* yrow = (y_all && g == 0 && ok) ? y_all + gi * M.L : nullptr;
+  float* yrow = (y_all && g == 0 && ok) ? y_all + (int64_t)gi * M.L : nullptr;
   if (yrow) yrow[0] = y;
 
-  const int nc = (d - 1) * C::RB;
   int c = 0;
   if (nc > 0) {
-    load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
     wait_chunk();
     __syncthreads();
   }
@@ -303,29 +312,85 @@ __device__ __forceinline__ void load_layer1(const ModelArgs& M, char* l1, int ti
   for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)M.chunks)[i];
 }
 
+// Exit depth of tile `tile` and this lane's point in it (-1: none; qi is
+// the lane's slot in the tile). The plan is the workgroup's LDS copy.
+template <int Q>
+__device__ __forceinline__ int tile_point(const QueryArgs& a, const Plan& plan, int64_t total,
+                                          int64_t tile, int qi, int& d) {
+  int64_t start, cnt;
+  if (tile >= total) {
+    d = 1;
+    return -1;
+  }
+  if (a.plan) {
+    decode_tile<Q>(&plan, a.m.L, tile, d, start, cnt);
+  } else {
+    d = a.full_depth;
+    start = tile * Q;
+    cnt = a.n - start < Q ? a.n - start : Q;
+  }
+  if (qi >= cnt) return -1;
+  return a.perm ? a.perm[start + qi] : (int)(start + qi);
+}
+
+__device__ __forceinline__ void point_coords(const float* __restrict__ xyz, int gi, float& x,
+                                             float& y, float& z) {
+  x = y = z = 0.0f;
+  if (gi >= 0) {
+    const float* p = xyz + 3 * (int64_t)gi;
+    x = p[0];
+    y = p[1];
+    z = p[2];
+  }
+}
+
+// Persistent: workgroup b runs tiles b, b + G, b + 2G, ... (G = grid size).
+// Point fetches are pipelined across tiles: while tile t runs, the
+// coordinates of tile t + G and the permutation entries of tile t + 2G are
+// in flight, so no tile starts on a dependent chain of global loads.
 template <int PREC, int WP>
 __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
   using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
   constexpr int Q = C::Q;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
+  __shared__ Plan splan;
   char* ring = lds;
   char* l1 = lds + C::NSLOT * C::CH;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   load_layer1<PREC, WP>(a.m, l1, tid);
+  if (a.plan)
+    for (int i = tid; i < (int)(sizeof(Plan) / 8); i += C::NT)
+      ((int64_t*)&splan)[i] = ((const int64_t*)a.plan)[i];
   __syncthreads();
-  const int64_t total = a.plan ? a.plan->total_tiles : (a.n + Q - 1) / Q;
-  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
-    int d;
-    int64_t start, cnt;
-    if (a.plan) {
-      decode_tile<Q>(a.plan, a.m.L, tile, d, start, cnt);
-    } else {
-      d = a.full_depth;
-      start = tile * Q;
-      cnt = a.n - start < Q ? a.n - start : Q;
-    }
-    run_tile<PREC, WP>(a.m, a.xyz, a.sdf, a.perm, start, cnt, d, ring, l1, lane, wave, a.y_all,
-                       a.dyn_r, a.depth_out);
+  const Plan& plan = splan;
+  const int64_t total = a.plan ? plan.total_tiles : (a.n + Q - 1) / Q;
+  const int64_t G = gridDim.x;
+  const int qi = wave * T::NQ + T::col(lane);
+  int64_t tile = blockIdx.x;
+  int d, d_next;
+  int gi = tile_point<Q>(a, plan, total, tile, qi, d);
+  int gi_next = tile_point<Q>(a, plan, total, tile + G, qi, d_next);
+  float px, py, pz;
+  point_coords(a.xyz, gi, px, py, pz);
+  // Consume the first loads here: otherwise the loop entry merges their
+  // pending state with the loop's and the first tile's layer-1 operands wait
+  // for every load issued in the loop body, prefetches included.
+  asm volatile("" ::"v"(gi_next), "v"(px), "v"(py), "v"(pz));
+  for (; tile < total; tile += G) {
+    int d_after;
+    const int gi_after = tile_point<Q>(a, plan, total, tile + 2 * G, qi, d_after);
+    float nx, ny, nz;
+    point_coords(a.xyz, gi_next, nx, ny, nz);
+    run_tile<PREC, WP>(a.m, a.sdf, d, gi, px, py, pz, ring, l1, lane, wave, a.y_all, a.dyn_r,
+                       a.depth_out);
+    d = d_next;
+    gi = gi_next;
+    px = nx;
+    py = ny;
+    pz = nz;
+    d_next = d_after;
+    gi_next = gi_after;
   }
 }
 
@@ -359,8 +424,12 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp_batch(BatchArgs a)
     int d;
     int64_t start, cnt;
     decode_tile<Q>(&q.plan, q.L, tile - q.tile0, d, start, cnt);
-    run_tile<PREC, WP>(M, q.xyz, q.sdf, q.perm, start, cnt, d, ring, l1, lane, wave, nullptr,
-                       0.0f, nullptr);
+    const int qi = wave * Tr<PREC>::NQ + Tr<PREC>::col(lane);
+    const int gi = qi < cnt ? q.perm[start + qi] : -1;
+    float px, py, pz;
+    point_coords(q.xyz, gi, px, py, pz);
+    run_tile<PREC, WP>(M, q.sdf, d, gi, px, py, pz, ring, l1, lane, wave, nullptr, 0.0f,
+                       nullptr);
   }
 }
 
