@@ -409,4 +409,6 @@ hipError_t launch_adjoint(int prec, const AdjointArgs& a, int grid, hipStream_t 
   return launch_adj_prec<PREC_FP16>(a, grid, s);
 }
 
+int adjoint_tile_points(int prec) { return prec == PREC_FP32 ? Cfg<PREC_FP32, 64>::Q : Cfg<PREC_BF16, 64>::Q; }
+
 }  // namespace sand

@@ -992,7 +992,7 @@ sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_
       return device_fail(e, "depth fill launch");
     return SAND_OK;
   }
-  sand_status st = run_bucketing(m, dm, xyz, n, sdf, nullptr, o, ws, s, tmlp_tile_points(prec), ev,
+  sand_status st = run_bucketing(m, dm, xyz, n, sdf, nullptr, o, ws, s, tmlp_tile_points(prec, m->WP), ev,
                                  &qa.perm, &qa.plan);
   if (st != SAND_OK) return st;
   if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
@@ -1114,13 +1114,13 @@ extern "C" sand_status sand_query_grad(sand_model m, sand_depthmap dm, const flo
     if (o.depth_out) e = launch_fill_u8(o.depth_out, n, (uint8_t)aa.q.full_depth, s);
     if (e != hipSuccess) st = device_fail(e, "depth fill launch");
   } else {
-    st = run_bucketing(m, dm, xyz, n, sdf, grad, o, ws, s, tmlp_tile_points(prec), nullptr,
+    st = run_bucketing(m, dm, xyz, n, sdf, grad, o, ws, s, adjoint_tile_points(prec), nullptr,
                        &aa.q.perm, &aa.q.plan);
   }
   if (st == SAND_OK) {
     int grid = m->num_cu;
     if (o.mode == SAND_FULL) {
-      const int64_t tiles = (n + tmlp_tile_points(prec) - 1) / tmlp_tile_points(prec);
+      const int64_t tiles = (n + adjoint_tile_points(prec) - 1) / adjoint_tile_points(prec);
       if (tiles < grid) grid = (int)tiles;
     }
     if ((e = launch_adjoint(prec, aa, grid, s)) != hipSuccess) st = device_fail(e, "adjoint launch");

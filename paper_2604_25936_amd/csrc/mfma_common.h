@@ -4,6 +4,13 @@
 
 #include "sand_internal.h"
 
+#ifndef SAND_PD
+#define SAND_PD 1
+#endif
+#ifndef SAND_FWD_WAVES
+#define SAND_FWD_WAVES 8
+#endif
+
 namespace sand {
 namespace mfma {
 
@@ -149,8 +156,16 @@ __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf
 template <int PREC, int WP>
 struct Cfg {
   using T = Tr<PREC>;
-  static constexpr int NW = 8;
+  static constexpr int NW = 8;                  // adjoint: wavefronts per workgroup
   static constexpr int NT = NW * 64;
+  // forward: NWF wavefronts per workgroup, WGF workgroups per CU (two
+  // wavefronts per SIMD either way)
+  // (layers wider than 256 keep one workgroup of eight: two rings would not
+  // fit in the CU's LDS)
+  static constexpr int NWF = WP > 256 ? 8 : SAND_FWD_WAVES;
+  static constexpr int NTF = NWF * 64;
+  static constexpr int WGF = 8 / NWF;
+  static constexpr int QF = NWF * T::NQ;         // forward points per tile
   static constexpr int Q = NW * T::NQ;          // points per tile
   static constexpr int RB = WP / T::BM;         // output blocks per layer
   static constexpr int KS = RB * T::SPB;        // K steps of a hidden product
@@ -162,7 +177,8 @@ struct Cfg {
   static constexpr int CH_B = TAIL_OFF_B + T::BM * 8;
   static constexpr int L1C = T::L1S * 256 + T::TAILB;    // layer-1 chunk bytes
   static constexpr int L1B = RB * L1C;
-  static constexpr int NSLOT = 3;                        // forward LDS ring slots
+  static constexpr int PD = SAND_PD;                     // forward chunks in flight
+  static constexpr int NSLOT = PD + 2;                   // forward LDS ring slots
   static constexpr int LDS = NSLOT * CH + L1B;
   static_assert(CH % 16 == 0 && CH_B % 16 == 0 && L1B % 16 == 0,
                 "chunks are whole 16-byte pieces");
@@ -200,6 +216,32 @@ __device__ __forceinline__ void load_chunk(const char* __restrict__ src, char* d
 }
 
 __device__ __forceinline__ void wait_chunk() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Number of loads one wavefront issues in load_chunk<BYTES, NW>.
+template <int BYTES, int NW>
+__device__ __forceinline__ int chunk_loads(int wave) {
+  constexpr int NP = BYTES / 16;
+  constexpr int WL = (NP + 64 * NW - 1) / (64 * NW);
+  int n = 0;
+#pragma unroll
+  for (int k = 0; k < WL; ++k) n += ((k * NW + wave) * 64 < NP) ? 1 : 0;
+  return __builtin_amdgcn_readfirstlane(n);   // uniform: the waits below branch on it
+}
+
+// Wait until at most n of this wavefront's vector memory operations are
+// outstanding. Loads return in issue order, so this completes every load
+// issued before the n most recent ones.
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+#define SAND_WAIT_VM(N) \
+  case N: asm volatile("s_waitcnt vmcnt(" #N ")" ::: "memory"); break;
+    SAND_WAIT_VM(1) SAND_WAIT_VM(2) SAND_WAIT_VM(3) SAND_WAIT_VM(4) SAND_WAIT_VM(5)
+    SAND_WAIT_VM(6) SAND_WAIT_VM(7) SAND_WAIT_VM(8) SAND_WAIT_VM(9) SAND_WAIT_VM(10)
+    SAND_WAIT_VM(11) SAND_WAIT_VM(12)
+#undef SAND_WAIT_VM
+    default: asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); break;
+  }
+}
 
 }  // namespace mfma
 }  // namespace sand

@@ -187,7 +187,8 @@ hipError_t launch_oct_samples(const int32_t* near_slots, const uint64_t* parents
 hipError_t launch_oct_finish(const int32_t* near_slots, int64_t nnear, const uint32_t* depth32,
                              uint8_t* depth, hipStream_t s);
 
-int tmlp_tile_points(int prec);
+int tmlp_tile_points(int prec, int WP);   // forward tile (the plan's tile_q for sand_query)
+int adjoint_tile_points(int prec);   // adjoint tile (the plan's tile_q for sand_query_grad)
 size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L);
 hipError_t launch_adjoint(int prec, const AdjointArgs& a, int grid, hipStream_t s);
 hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s);

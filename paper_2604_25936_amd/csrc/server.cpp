@@ -205,7 +205,7 @@ void sand_server_s::launch(Slot* s) {
     e = hipMemcpyAsync(s->desc_dev, s->desc_host, nreq * sizeof(BatchReq), hipMemcpyHostToDevice,
                        s->stream);
   if (e == hipSuccess)
-    e = launch_bucketing_batch(s->desc_dev, nreq, nblk, 0, tmlp_tile_points(prec), s->total_dev,
+    e = launch_bucketing_batch(s->desc_dev, nreq, nblk, 0, tmlp_tile_points(prec, WP), s->total_dev,
                                s->stream);
   if (e == hipSuccess) {
     BatchArgs ba{s->desc_dev, nreq, s->total_dev};

@@ -26,13 +26,20 @@
 //    flight while chunk c feeds the MFMAs.
 //  * Software pipelining: each wavefront issues the MFMAs of block rb
 //    together with the sine/tail epilogue of block rb-1.
-//  * Eight wavefronts per workgroup, two per SIMD: while one wavefront runs
-//    its sine/tail epilogue on the vector ALU the other keeps the matrix
-//    core busy.
-// The grid is persistent (one workgroup per CU) and strides over tiles,
-// which the plan orders deepest bucket first.
+//  * Two wavefronts per SIMD: while one wavefront runs its sine/tail
+//    epilogue on the vector ALU the other keeps the matrix core busy. By
+//    default one workgroup of eight wavefronts per CU shares each weight
+//    chunk among 256 points; SAND_FWD_WAVES=4 builds two independent
+//    workgroups of four per CU instead (each with its own ring), which
+//    measured slower on the 8x256 model (twice the weight traffic).
+// The grid is persistent and strides over tiles, which the plan orders
+// deepest bucket first.
 
 #include "mfma_common.h"
+
+#ifndef SAND_APF
+#define SAND_APF 4
+#endif
 
 namespace sand {
 
@@ -63,6 +70,50 @@ __device__ __forceinline__ void tail_fma16(float& s0, float& s1, float w0, float
         "v"(h[6]), "v"(h[7]), "v"(h[8]), "v"(h[9]), "v"(h[10]), "v"(h[11]), "v"(h[12]),
         "v"(h[13]), "v"(h[14]), "v"(h[15]));
 #undef SAND_TAIL_E
+}
+
+// One register's share of the BF16/FP16 tail sums: s0 += a0[unit(E)] h and
+// s1 += a1[unit(E)] h, the weights broadcast from lane E of each 16-lane row
+// (as in tail_fma16). The s_nop covers the wait states a DPP read of w0, w1
+// needs after a VALU write of them.
+template <int E>
+__device__ __forceinline__ void tail_pair(float& s0, float& s1, float w0, float w1, float h);
+#define SAND_TAIL_PAIR(E)                                                                       \
+  template <>                                                                                   \
+  __device__ __forceinline__ void tail_pair<E>(float& s0, float& s1, float w0, float w1,        \
+                                               float h) {                                       \
+    asm("s_nop 1\n\t"                                                                           \
+        "v_fmac_f32_dpp %0, %2, %4 row_newbcast:" #E " row_mask:0xf bank_mask:0xf\n\t"           \
+        "v_fmac_f32_dpp %1, %3, %4 row_newbcast:" #E " row_mask:0xf bank_mask:0xf"               \
+        : "+v"(s0), "+v"(s1)                                                                    \
+        : "v"(w0), "v"(w1), "v"(h));                                                            \
+  }
+SAND_TAIL_PAIR(0) SAND_TAIL_PAIR(1) SAND_TAIL_PAIR(2) SAND_TAIL_PAIR(3)
+SAND_TAIL_PAIR(4) SAND_TAIL_PAIR(5) SAND_TAIL_PAIR(6) SAND_TAIL_PAIR(7)
+SAND_TAIL_PAIR(8) SAND_TAIL_PAIR(9) SAND_TAIL_PAIR(10) SAND_TAIL_PAIR(11)
+SAND_TAIL_PAIR(12) SAND_TAIL_PAIR(13) SAND_TAIL_PAIR(14) SAND_TAIL_PAIR(15)
+#undef SAND_TAIL_PAIR
+
+__device__ __forceinline__ void tail_pair_at(int e, float& s0, float& s1, float w0, float w1,
+                                             float h) {
+  switch (e) {   // e is a constant once the caller's loops are unrolled
+    case 0: tail_pair<0>(s0, s1, w0, w1, h); break;
+    case 1: tail_pair<1>(s0, s1, w0, w1, h); break;
+    case 2: tail_pair<2>(s0, s1, w0, w1, h); break;
+    case 3: tail_pair<3>(s0, s1, w0, w1, h); break;
+    case 4: tail_pair<4>(s0, s1, w0, w1, h); break;
+    case 5: tail_pair<5>(s0, s1, w0, w1, h); break;
+    case 6: tail_pair<6>(s0, s1, w0, w1, h); break;
+    case 7: tail_pair<7>(s0, s1, w0, w1, h); break;
+    case 8: tail_pair<8>(s0, s1, w0, w1, h); break;
+    case 9: tail_pair<9>(s0, s1, w0, w1, h); break;
+    case 10: tail_pair<10>(s0, s1, w0, w1, h); break;
+    case 11: tail_pair<11>(s0, s1, w0, w1, h); break;
+    case 12: tail_pair<12>(s0, s1, w0, w1, h); break;
+    case 13: tail_pair<13>(s0, s1, w0, w1, h); break;
+    case 14: tail_pair<14>(s0, s1, w0, w1, h); break;
+    default: tail_pair<15>(s0, s1, w0, w1, h); break;
+  }
 }
 
 // Epilogue of one output block: sine, tail partial sums, pack for the next layer.
@@ -132,7 +183,10 @@ __device__ __forceinline__ float add_tail(float y, float s0, float s1, float c0,
 }
 
 // MFMA chain of one output block: bias + W_j h over all K steps, A operands
-// from the LDS slot holding the block's chunk.
+// from the LDS slot holding the block's chunk. The A operands are read PF
+// steps ahead of their MFMA; the scheduling groups keep the compiler from
+// sinking each read to its use, which would make every MFMA of the chain
+// wait for a full LDS round trip.
 template <int PREC, int WP>
 __device__ __forceinline__ typename Tr<PREC>::Acc block_mma(
     const char* slot, int lane, const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
@@ -140,20 +194,119 @@ __device__ __forceinline__ typename Tr<PREC>::Acc block_mma(
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
-  typename T::Acc acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb,
-                               typename T::Acc{});
+  constexpr int NS = C::KS + 1;          // the bias step, then the KS weight steps
+  constexpr int PF_WANT = WP > 256 ? 1 : SAND_APF;   // wider layers have no registers to spare
+  constexpr int PF = NS < PF_WANT ? NS : PF_WANT;
+  // the bias tile sits after the KS weight tiles in the chunk
+  auto a_of = [&](int s) -> V {
+    return *(const V*)(slot + ((s == 0 ? C::KS : s - 1) * 64 + lane) * T::VB);
+  };
+  V a[PF];
 #pragma unroll
-  for (int s = 0; s < C::KS; ++s) acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
+  for (int s = 0; s < PF; ++s) a[s] = a_of(s);
+  typename T::Acc acc = {};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const V cur = a[s % PF];
+    if (s + PF < NS) a[s % PF] = a_of(s + PF);
+    acc = T::mma(cur, s == 0 ? bb : in[s - 1], acc);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x100, PF, 0);
+#pragma unroll
+  for (int s = 0; s < NS - PF; ++s) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, PF, 0);
   return acc;
 }
 
-// One hidden layer: in -> out, streaming its RB chunks through a three-slot
-// LDS ring. Software-pipelined: the MFMAs of block rb are issued together
+// One block step of a BF16/FP16 hidden layer, scheduled by hand: the 17
+// MFMAs of block rb (bias step first) each carry a share of block rb-1's
+// epilogue (one sine, one tail pair, every other step one pack), so that a
+// wavefront keeps the matrix core and the vector ALU busy together instead
+// of alternating between an MFMA phase and a vector phase in step with the
+// other wavefront of its SIMD. A operands arrive in batches of four, one
+// batch ahead; each batch is awaited before the next is requested, so no
+// wait covers a read issued just before it.
+template <int PREC, int WP, bool EPI>
+__device__ __forceinline__ typename Tr<PREC>::Acc block_step16(
+    const char* slot, const char* ptails, int lane, int rbp,
+    const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS], const typename Tr<PREC>::V& bb,
+    const typename Tr<PREC>::Acc& prev, typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
+    float& s0, float& s1) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  constexpr int NS = C::KS + 1;
+  constexpr int NB = (NS + 3) / 4;
+  auto a_of = [&](int s) -> V {
+    return *(const V*)(slot + ((s == 0 ? C::KS : s - 1) * 64 + lane) * T::VB);
+  };
+  float w0 = 0.0f, w1 = 0.0f;
+  if constexpr (EPI) {
+    w0 = ((const float*)ptails)[lane];
+    w1 = ((const float*)ptails)[64 + lane];
+  }
+  V a[2][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k < NS) a[0][k] = a_of(k);
+  float h[16];
+  typename T::Acc acc = {};
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (4 * b + k < NS) asm volatile("" ::"v"(a[b & 1][k]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (4 * (b + 1) + k < NS) a[(b + 1) & 1][k] = a_of(4 * (b + 1) + k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int s = 4 * b + k;
+      if (s < NS) {
+        acc = T::mma(a[b & 1][k], s == 0 ? bb : in[s - 1], acc);
+        if constexpr (EPI) {
+          if (s < 16) h[s] = sin_rev(prev[s]);
+          if (s >= 2 && s - 2 < 16) tail_pair_at(s - 2, s0, s1, w0, w1, h[s - 2]);
+          if (s >= 2 && (s & 1) == 0 && s - 1 < 16) {
+            T::template put<C::KS>(out, rbp, s - 2, h[s - 2]);
+            T::template put<C::KS>(out, rbp, s - 1, h[s - 1]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  if constexpr (EPI) {
+    // blocks with fewer than 16 MFMA steps finish their epilogue here
+#pragma unroll
+    for (int e = NS; e < 16; ++e) h[e] = sin_rev(prev[e]);
+#pragma unroll
+    for (int e = NS - 2; e < 16; ++e) tail_pair_at(e, s0, s1, w0, w1, h[e]);
+#pragma unroll
+    for (int e = (NS & ~1); e < 16; e += 2) {
+      T::template put<C::KS>(out, rbp, e, h[e]);
+      T::template put<C::KS>(out, rbp, e + 1, h[e + 1]);
+    }
+  }
+  return acc;
+}
+
+#ifndef SAND_INTERLEAVE
+#define SAND_INTERLEAVE 1
+#endif
+
+// One hidden layer: in -> out, streaming its RB chunks through an LDS ring of
+// PD + 2 slots. Software-pipelined: the MFMAs of block rb are issued together
 // with the (independent) sine/tail epilogue of block rb-1, so one
 // wavefront keeps the matrix core and the vector ALU busy at once. Chunk c
-// lives in slot c % 3; while block rb (chunk c) feeds the MFMAs and block
-// rb-1's tail weights (chunk c-1) feed the epilogue, chunk c+1 streams into
-// the third slot. c is the tile's running chunk index, nc its chunk count.
+// lives in slot c % (PD + 2); while block rb (chunk c) feeds the MFMAs and
+// block rb-1's tail weights (chunk c-1) feed the epilogue, chunks c+1 .. c+PD
+// stream into the other slots (PD chunks in flight hide the latency of the
+// global-to-LDS copies). c is the tile's running chunk index, nc its chunk
+// count.
 template <int PREC, int WP>
 __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ hidden, char* ring,
                                               int wave, int lane, int g, int& c, int nc,
@@ -165,21 +318,39 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
   using V = typename T::V;
   float s0 = 0.0f, s1 = 0.0f;
   const V bb = T::bias_b(g);
+  const int lpc = chunk_loads<C::CH, C::NWF>(wave);
   typename T::Acc prev = {};
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb) {
-    const bool pre = c + 1 < nc;
-    if (pre)
-      load_chunk<C::CH, C::NW>(hidden + (size_t)(c + 1) * C::CH,
-                               ring + ((c + 1) % C::NSLOT) * C::CH, wave, lane);
-    const typename T::Acc acc = block_mma<PREC, WP>(ring + (c % C::NSLOT) * C::CH, lane, in, bb);
-    if (rb > 0) {
-      epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, lane, g,
-                            rb - 1,
-                            prev, out, s0, s1);
-      pin_block<PREC, C::KS>(out, rb - 1, s0, s1);
+    if (c + C::PD < nc)
+      load_chunk<C::CH, C::NWF>(hidden + (size_t)(c + C::PD) * C::CH,
+                               ring + ((c + C::PD) % C::NSLOT) * C::CH, wave, lane);
+    typename T::Acc acc;
+    if constexpr (T::VB == 16 && WP <= 256 && SAND_INTERLEAVE) {
+      const char* ptails = ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF;
+      if (rb > 0) {
+        acc = block_step16<PREC, WP, true>(ring + (c % C::NSLOT) * C::CH, ptails, lane, rb - 1, in,
+                                           bb, prev, out, s0, s1);
+        pin_block<PREC, C::KS>(out, rb - 1, s0, s1);
+      } else {
+        acc = block_step16<PREC, WP, false>(ring + (c % C::NSLOT) * C::CH, ptails, lane, 0, in, bb,
+                                            prev, out, s0, s1);
+      }
+    } else {
+      acc = block_mma<PREC, WP>(ring + (c % C::NSLOT) * C::CH, lane, in, bb);
+      if (rb > 0) {
+        epilogue<PREC, C::KS>(ring + ((c + C::NSLOT - 1) % C::NSLOT) * C::CH + C::TAIL_OFF, lane,
+                              g, rb - 1, prev, out, s0, s1);
+        pin_block<PREC, C::KS>(out, rb - 1, s0, s1);
+      }
     }
-    if (pre) wait_chunk();
+    if (c + 1 < nc) {
+      // chunk c+1 has landed once only the loads of chunks c+2 .. c+PD remain
+      int later = 0;
+#pragma unroll
+      for (int k = 2; k <= C::PD; ++k) later += (c + k < nc) ? lpc : 0;
+      wait_vm(later);
+    }
     __syncthreads();
     prev = acc;
     ++c;
@@ -250,10 +421,13 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
   const char* hidden = M.chunks + C::L1B;
   const bool ok = gi >= 0;
 
-  // The first hidden chunk streams into the ring while layer 1 runs (layer 1
-  // reads only its own LDS region; every ring slot is free at a tile's start).
+  // The first PD hidden chunks stream into the ring while layer 1 runs (layer
+  // 1 reads only its own LDS region; every ring slot is free at a tile's
+  // start).
   const int nc = (d - 1) * C::RB;
-  if (nc > 0) load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
+#pragma unroll
+  for (int k = 0; k < C::PD; ++k)
+    if (k < nc) load_chunk<C::CH, C::NWF>(hidden + (size_t)k * C::CH, ring + k * C::CH, wave, lane);
 
   V actA[C::KS], actB[C::KS];
   float s0 = 0.0f, s1 = 0.0f;
@@ -268,7 +442,11 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
 
   int c = 0;
   if (nc > 0) {
-    wait_chunk();
+    const int lpc = chunk_loads<C::CH, C::NWF>(wave);
+    int later = 0;   // loads of chunks 1 .. PD-1
+#pragma unroll
+    for (int k = 1; k < C::PD; ++k) later += (k < nc) ? lpc : 0;
+    wait_vm(later);
     __syncthreads();
   }
   // Map-free early exit (dyn_r > 0): a point's output is frozen after the
@@ -301,15 +479,19 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
     if (!after_layer(j + 1, yn, t)) break;
   }
   if (depth_out && g == 0 && ok) depth_out[gi] = (uint8_t)(dyn_r > 0.0f ? dexit : d);
-  // the last epilogue read a ring slot the next tile's first load may reuse
-  if (nc > 0) __syncthreads();
+  // the last epilogue read a ring slot the next tile's first load may reuse,
+  // and an early exit can leave chunk copies in flight
+  if (nc > 0) {
+    wait_chunk();
+    __syncthreads();
+  }
   if (g == 0 && ok) sdf[gi] = y;
 }
 
 template <int PREC, int WP>
 __device__ __forceinline__ void load_layer1(const ModelArgs& M, char* l1, int tid) {
   using C = Cfg<PREC, WP>;
-  for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)M.chunks)[i];
+  for (int i = tid; i < C::L1B / 16; i += C::NTF) ((uint4*)l1)[i] = ((const uint4*)M.chunks)[i];
 }
 
 // Exit depth of tile `tile` and this lane's point in it (-1: none; qi is
@@ -349,10 +531,11 @@ __device__ __forceinline__ void point_coords(const float* __restrict__ xyz, int 
 // coordinates of tile t + G and the permutation entries of tile t + 2G are
 // in flight, so no tile starts on a dependent chain of global loads.
 template <int PREC, int WP>
-__global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
+__global__ __launch_bounds__((Cfg<PREC, WP>::NTF)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_tmlp(QueryArgs a) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
-  constexpr int Q = C::Q;
+  constexpr int Q = C::QF;
   __shared__ __attribute__((aligned(16))) char lds[C::LDS];
   __shared__ Plan splan;
   char* ring = lds;
@@ -360,7 +543,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   load_layer1<PREC, WP>(a.m, l1, tid);
   if (a.plan)
-    for (int i = tid; i < (int)(sizeof(Plan) / 8); i += C::NT)
+    for (int i = tid; i < (int)(sizeof(Plan) / 8); i += C::NTF)
       ((int64_t*)&splan)[i] = ((const int64_t*)a.plan)[i];
   __syncthreads();
   const Plan& plan = splan;
@@ -398,9 +581,10 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp(QueryArgs a) {
 // in one persistent launch: tile t belongs to the last query whose first
 // tile is <= t. Layer-1 weights are reloaded into LDS when the model changes.
 template <int PREC, int WP>
-__global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp_batch(BatchArgs a) {
+__global__ __launch_bounds__((Cfg<PREC, WP>::NTF)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_tmlp_batch(BatchArgs a) {
   using C = Cfg<PREC, WP>;
-  constexpr int Q = C::Q;
+  constexpr int Q = C::QF;
   __shared__ __attribute__((aligned(16))) char ring[C::NSLOT * C::CH];
   __shared__ __attribute__((aligned(16))) char l1[C::L1B];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -436,13 +620,13 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_tmlp_batch(BatchArgs a)
 template <int PREC, int WP>
 hipError_t launch_one(const QueryArgs& a, int num_cu, hipStream_t s) {
   using C = Cfg<PREC, WP>;
-  int64_t grid = num_cu;
+  int64_t grid = (int64_t)num_cu * C::WGF;
   if (!a.plan) {
-    const int64_t tiles = (a.n + C::Q - 1) / C::Q;
+    const int64_t tiles = (a.n + C::QF - 1) / C::QF;
     if (tiles < grid) grid = tiles;
   }
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL((k_tmlp<PREC, WP>), dim3((unsigned)grid), dim3(C::NT), 0, s, a);
+  hipLaunchKernelGGL((k_tmlp<PREC, WP>), dim3((unsigned)grid), dim3(C::NTF), 0, s, a);
   return hipGetLastError();
 }
 
@@ -459,7 +643,8 @@ hipError_t launch_prec(const QueryArgs& a, int num_cu, hipStream_t s) {
 
 template <int PREC, int WP>
 hipError_t launch_batch_one(const BatchArgs& a, int num_cu, hipStream_t s) {
-  hipLaunchKernelGGL((k_tmlp_batch<PREC, WP>), dim3((unsigned)num_cu), dim3(Cfg<PREC, WP>::NT), 0,
+  hipLaunchKernelGGL((k_tmlp_batch<PREC, WP>), dim3((unsigned)(num_cu * Cfg<PREC, WP>::WGF)),
+                     dim3(Cfg<PREC, WP>::NTF), 0,
                      s, a);
   return hipGetLastError();
 }
@@ -477,7 +662,10 @@ hipError_t launch_batch_prec(int WP, const BatchArgs& a, int num_cu, hipStream_t
 
 }  // namespace
 
-int tmlp_tile_points(int prec) { return 8 * (prec == PREC_FP32 ? 16 : 32); }
+int tmlp_tile_points(int prec, int WP) {
+  const int nq = prec == PREC_FP32 ? 16 : 32;
+  return (WP > 256 ? 8 : SAND_FWD_WAVES) * nq;
+}
 
 hipError_t launch_tmlp_batch(int prec, int WP, const BatchArgs& a, int num_cu, hipStream_t s) {
   if (prec == PREC_FP32) return launch_batch_prec<PREC_FP32>(WP, a, num_cu, s);
