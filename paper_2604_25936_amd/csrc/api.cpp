@@ -895,7 +895,8 @@ WorkspaceLayout workspace_layout(int64_t n) {
   w.perm = al((size_t)n);
   w.counts = w.perm + al(4 * (size_t)n);
   w.plan = w.counts + al(nblk * kBuckets * 4);
-  w.total = w.plan + al(sizeof(Plan));
+  w.groups = w.plan + al(sizeof(Plan));
+  w.total = w.groups + al((nblk + kScanGroup - 1) / kScanGroup * kBuckets * 4);
   w.nblk = (int64_t)nblk;
   return w;
 }
@@ -953,7 +954,8 @@ sand_status run_bucketing(sand_model m, sand_depthmap dm, const float* xyz, int6
                                sdf, grad, counts, s)) != hipSuccess)
     return device_fail(e, "lookup launch");
   mark(1);
-  if ((e = launch_scan(counts, w.nblk, m->L, tile_q, plan, s)) != hipSuccess)
+  if ((e = launch_scan(counts, w.nblk, m->L, tile_q, plan, (int32_t*)(ws + w.groups), s)) !=
+      hipSuccess)
     return device_fail(e, "scan launch");
   mark(2);
   if ((e = launch_scatter(depth, n, counts, perm, s)) != hipSuccess)

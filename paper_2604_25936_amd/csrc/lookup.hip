@@ -1,21 +1,25 @@
 // Depth lookup and stable bucketing of query points by exit depth.
 //
 // Inference first reads every point's exit depth from the network-depth map
-// and answers far-field points (depth 0) from the stored value (Sec. 3.4,
-// Eq. 7); the remaining points are evaluated to their own depth. To run
-// points of equal depth together, three launches build a permutation that
-// groups point indices by depth, stable within each group:
+// (a dense grid or the sparse octree) and answers far-field points (depth
+// 0) from the stored value (Sec. 3.4, Eq. 7); the remaining points are
+// evaluated to their own depth. To run points of equal depth together, three
+// steps build a permutation that groups point indices by depth, stable
+// within each group:
 //   1. k_lookup_count: per 4096-point chunk, depth per point (written as
 //      uint8), far values written straight to the output, and a per-chunk
 //      histogram built from wavefront ballots;
 //   2. k_scan: one workgroup turns the per-chunk histograms into per-chunk
-//      output offsets and writes the tile plan (deepest bucket first);
+//      output offsets and writes the tile plan (deepest bucket first); large
+//      queries first sum groups of chunks in parallel (k_group_sums), scan
+//      the group sums, and expand them per chunk (k_group_offsets);
 //   3. k_scatter: per chunk again, each point's rank among equal depths
-//      (ballot + popcount below the lane) gives its slot in the permutation.
-// Point coordinates are read through LDS so that every global load of a
-// wavefront covers 256 contiguous bytes. Batched variants run the same
-// bodies for several queries in one launch (each lookup block belongs to
-// one query; one scan workgroup per query).
+//      (ballots + popcounts below the lane) gives its slot in the
+//      permutation.
+// Every thread takes four consecutive points per round, so a wavefront's
+// coordinate loads cover 3 KB of contiguous memory in 16-byte pieces.
+// Batched variants run the same bodies for several queries in one launch
+// (each lookup block belongs to one query; one scan workgroup per query).
 
 #include "sand_internal.h"
 
@@ -23,7 +27,6 @@ namespace sand {
 
 namespace {
 
-constexpr int kRounds = kLookupChunk / kLookupThreads;
 
 __device__ __forceinline__ int cell_index(float x, float s, int half) {
   // x * s is exact (s a power of two); clamp before the float->int step so
@@ -34,39 +37,82 @@ __device__ __forceinline__ int cell_index(float x, float s, int half) {
   return (int)floorf(v) + half;
 }
 
-// Leaf of the octree holding a point: its stored depth d and far value v.
-// The point's cell at level D follows from the exact cell rule; its cell at
-// every coarser level is that index shifted right. The descent follows
-// internal nodes from the root; a node's child slot is 8 rank(parent) +
-// child, rank counting the internal nodes before it at its level.
-__device__ __forceinline__ void octree_leaf(const OctreeArgs& o, float x, float y, float z,
-                                            int& d, float& v) {
+// Leaves of the octree holding P points: stored depth d and far value v
+// of each. A point's cell at level D follows from the exact cell rule; its
+// cell at every coarser level is that index shifted right. The descents run
+// level by level together so that their loads overlap. At level l the word
+// holding the parent's bit (level l-1) is already in hand; the parent's
+// rank word and the word holding the child's bit are loaded together: the
+// child's slot is 8 rank(parent) + child, and the child is internal when its
+// bit is set (only below level D). A leaf's depth and value are loaded last.
+template <int P>
+__device__ __forceinline__ void octree_leaves(const OctreeArgs& o, const float (&x)[P],
+                                              const float (&y)[P], const float (&z)[P],
+                                              int (&d)[P], float (&v)[P]) {
   if (o.root_leaf) {
-    d = 0;
-    v = o.root_value;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      d[i] = 0;
+      v[i] = o.root_value;
+    }
     return;
   }
   const int D = o.D, half = 1 << (D - 1);
   const float s = (float)half;
-  const int ix = cell_index(x, s, half), iy = cell_index(y, s, half), iz = cell_index(z, s, half);
-  uint64_t p = 0;   // code of the internal node at level l-1 holding the point
-  for (int l = 1; l <= D; ++l) {
-    const int sh = D - l;
-    const int child = (((ix >> sh) & 1) << 2) | (((iy >> sh) & 1) << 1) | ((iz >> sh) & 1);
-    const uint64_t w = o.bits[l - 1][p >> 6];
-    const uint64_t rk = o.rank[l - 1][p >> 6] + __popcll(w & ((1ull << (p & 63)) - 1ull));
-    const uint64_t slot = 8ull * rk + (uint64_t)child;
-    const uint64_t m = 8ull * p + (uint64_t)child;
-    if (l < D && ((o.bits[l][m >> 6] >> (m & 63)) & 1ull)) {
-      p = m;
-      continue;
-    }
-    d = o.depth[l][slot];
-    v = o.value[l][slot];
-    return;
+  int ix[P], iy[P], iz[P];
+  uint32_t p[P];      // code of the internal node holding the point (level l-1)
+  uint64_t w[P];      // the bitmask word holding p's bit
+  bool live[P];
+  const uint64_t w0 = o.bits[0][0];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    ix[i] = cell_index(x[i], s, half);
+    iy[i] = cell_index(y[i], s, half);
+    iz[i] = cell_index(z[i], s, half);
+    p[i] = 0;
+    w[i] = w0;
+    live[i] = true;
+    d[i] = 0;
+    v[i] = __builtin_nanf("");
   }
-  d = 0;                      // not reached: level D has no internal nodes
-  v = __builtin_nanf("");
+  for (int l = 1; l <= D; ++l) {
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < P; ++i) any |= live[i];
+    if (!any) break;
+    const int sh = D - l;
+    const uint32_t* rank = o.rank[l - 1];
+    const uint64_t* bits = l < D ? o.bits[l] : nullptr;
+    uint32_t rk[P];
+    uint64_t wn[P];
+    uint32_t m[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const uint32_t child = (((ix[i] >> sh) & 1) << 2) | (((iy[i] >> sh) & 1) << 1) |
+                             ((iz[i] >> sh) & 1);
+      m[i] = 8u * p[i] + child;
+      rk[i] = 0;
+      wn[i] = 0;
+      if (live[i]) {
+        rk[i] = rank[p[i] >> 6];
+        if (bits) wn[i] = bits[m[i] >> 6];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      if (!live[i]) continue;
+      const uint32_t r = rk[i] + (uint32_t)__popcll(w[i] & ((1ull << (p[i] & 63)) - 1ull));
+      const uint32_t slot = 8u * r + (m[i] & 7u);
+      if ((wn[i] >> (m[i] & 63)) & 1ull) {
+        p[i] = m[i];
+        w[i] = wn[i];
+      } else {
+        d[i] = o.depth[l][slot];
+        v[i] = o.value[l][slot];
+        live[i] = false;
+      }
+    }
+  }
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -89,60 +135,99 @@ __device__ __forceinline__ void wave_histogram(int d, bool valid, int* hist) {
 }
 
 // Body of one lookup block: points [blk*4096, blk*4096 + 4096) of one query.
+// Each thread takes kPP consecutive points per round, kQuadRounds rounds; a
+// wavefront's round covers 3 KB of contiguous coordinates, read with 16-byte
+// loads (all rounds' loads are issued before any point is looked up).
+constexpr int kPP = 4;
+constexpr int kQuadRounds = kLookupChunk / (kLookupThreads * kPP);
+
 __device__ __forceinline__ void lookup_block(
     int64_t blk, const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
     int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
     const uint8_t* __restrict__ forced, int mode, int L, int max_depth,
     uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
     int32_t* __restrict__ counts) {
-  __shared__ float sx[3 * kLookupThreads];
   __shared__ int hist[kBuckets];
   const int t = threadIdx.x;
   if (t < kBuckets) hist[t] = 0;
   const int64_t base = blk * kLookupChunk;
   const int half = R >> 1;
   const float s = (float)half;
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t q0 = base + (int64_t)r * kLookupThreads;
-    if (q0 >= n) break;
-    __syncthreads();
-    for (int k = 0; k < 3; ++k) {
-      const int64_t f = q0 * 3 + k * kLookupThreads + t;
-      sx[k * kLookupThreads + t] = f < 3 * n ? xyz[f] : 0.0f;
+  const bool vec_in = ((uintptr_t)xyz & 15) == 0;
+  float pt[kQuadRounds][3 * kPP];
+#pragma unroll
+  for (int r = 0; r < kQuadRounds; ++r) {
+    const int64_t q0 = base + ((int64_t)r * kLookupThreads + t) * kPP;
+    if (vec_in && q0 + kPP <= n) {
+      const float4* src = (const float4*)(xyz + 3 * q0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float4 f = src[k];
+        pt[r][4 * k] = f.x;
+        pt[r][4 * k + 1] = f.y;
+        pt[r][4 * k + 2] = f.z;
+        pt[r][4 * k + 3] = f.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 3 * kPP; ++k) pt[r][k] = 3 * q0 + k < 3 * n ? xyz[3 * q0 + k] : 0.0f;
     }
-    __syncthreads();
-    const int64_t q = q0 + t;
-    const bool valid = q < n;
-    int d = 0;
-    if (valid) {
-      const float x = sx[3 * t], y = sx[3 * t + 1], z = sx[3 * t + 2];
-      int cell = -1;
-      float farv = __builtin_nanf("");   // octree: the leaf's value; dense: read below
-      int od = 0;
-      if (oct != nullptr) {
-        if (mode != 1) octree_leaf(*oct, x, y, z, od, farv);
-      } else if (map != nullptr) {
-        const int ix = cell_index(x, s, half), iy = cell_index(y, s, half),
-                  iz = cell_index(z, s, half);
-        cell = (ix * R + iy) * R + iz;
-      }
-      if (mode == 1) {
-        d = L;
-      } else if (mode == 2) {
-        d = forced[q];
-        if (d > L) d = L;
-      } else {
-        d = oct != nullptr ? od : map[cell];
-      }
-      if (max_depth > 0 && d > max_depth) d = max_depth;
-      depth[q] = (uint8_t)d;
-      if (d == 0) {
-        if (oct == nullptr && far != nullptr && cell >= 0) farv = far[cell];
-        if (sdf) sdf[q] = farv;
-        if (grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
+  }
+  __syncthreads();   // hist cleared
+#pragma unroll
+  for (int r = 0; r < kQuadRounds; ++r) {
+    const int64_t q0 = base + ((int64_t)r * kLookupThreads + t) * kPP;
+    float x[kPP], y[kPP], z[kPP], farv[kPP];
+    int d[kPP], cell[kPP];
+#pragma unroll
+    for (int i = 0; i < kPP; ++i) {
+      x[i] = pt[r][3 * i];
+      y[i] = pt[r][3 * i + 1];
+      z[i] = pt[r][3 * i + 2];
+      cell[i] = -1;
+      farv[i] = __builtin_nanf("");
+      d[i] = 0;
+    }
+    // the map's depth (and, for an octree, the leaf's value) of every point;
+    // FORCED mode keeps the map's far value for points forced to depth 0
+    if (oct != nullptr) {
+      if (mode != 1) octree_leaves<kPP>(*oct, x, y, z, d, farv);
+    } else if (map != nullptr) {
+#pragma unroll
+      for (int i = 0; i < kPP; ++i)
+        cell[i] = (cell_index(x[i], s, half) * R + cell_index(y[i], s, half)) * R +
+                  cell_index(z[i], s, half);
+      if (mode == 0) {
+#pragma unroll
+        for (int i = 0; i < kPP; ++i) d[i] = map[cell[i]];
       }
     }
-    wave_histogram(d, valid, hist);
+    if (mode == 1) {
+#pragma unroll
+      for (int i = 0; i < kPP; ++i) d[i] = L;
+    } else if (mode == 2) {
+#pragma unroll
+      for (int i = 0; i < kPP; ++i) {
+        const int dd = q0 + i < n ? forced[q0 + i] : 0;
+        d[i] = dd > L ? L : dd;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPP; ++i) {
+      const int64_t q = q0 + i;
+      const bool valid = q < n;
+      if (max_depth > 0 && d[i] > max_depth) d[i] = max_depth;
+      if (!valid) d[i] = 0;
+      if (valid) {
+        depth[q] = (uint8_t)d[i];
+        if (d[i] == 0) {
+          if (oct == nullptr && far != nullptr && cell[i] >= 0) farv[i] = far[cell[i]];
+          if (sdf) sdf[q] = farv[i];
+          if (grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
+        }
+      }
+      wave_histogram(d[i], valid, hist);
+    }
   }
   __syncthreads();
   if (t < kBuckets) counts[blk * kBuckets + t] = hist[t];
@@ -158,31 +243,63 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
                grad, counts);
 }
 
-constexpr int kScanThreads = 256;
+constexpr int kScanThreads = 1024;
 
 // One workgroup: per-chunk histograms -> per-chunk bucket offsets (in
 // place) and the tile plan. Bucket d >= 1 occupies perm slots
 // [start[d], start[d] + count[d]); depth-0 points are not in the permutation.
+// Thread t owns a contiguous range of chunks: it sums them, the per-bucket
+// exclusive prefix over threads comes from a wavefront scan (shuffles) and a
+// scan of the sixteen wavefront totals, and the thread then rewrites its
+// chunks' counts as running offsets.
 __device__ __forceinline__ void scan_body(int32_t* __restrict__ counts, int64_t nblk, int L,
                                           int tile_q, Plan* __restrict__ plan) {
-  __shared__ int64_t part[kScanThreads][kBuckets];
+  constexpr int NWAVE = kScanThreads / 64;
+  __shared__ int64_t wtot[NWAVE][kBuckets];
   __shared__ int64_t start[kBuckets];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t per = (nblk + kScanThreads - 1) / kScanThreads;
-  const int64_t b0 = t * per;
+  const int64_t b0 = t * per < nblk ? t * per : nblk;
   const int64_t b1 = b0 + per < nblk ? b0 + per : nblk;
   int64_t sum[kBuckets];
+#pragma unroll
   for (int d = 0; d < kBuckets; ++d) sum[d] = 0;
-  for (int64_t b = b0; b < b1; ++b)
+  int64_t b = b0;
+  for (; b + 4 <= b1; b += 4) {
+    int32_t c[4][kBuckets];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int d = 0; d < kBuckets; ++d) c[k][d] = counts[(b + k) * kBuckets + d];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int d = 0; d < kBuckets; ++d) sum[d] += c[k][d];
+  }
+  for (; b < b1; ++b)
+#pragma unroll
     for (int d = 0; d < kBuckets; ++d) sum[d] += counts[b * kBuckets + d];
-  for (int d = 0; d < kBuckets; ++d) part[t][d] = sum[d];
+  // inclusive scan over the wavefront's lanes, bucket by bucket
+  int64_t incl[kBuckets];
+#pragma unroll
+  for (int d = 0; d < kBuckets; ++d) {
+    int64_t v = sum[d];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t u = __shfl_up(v, off);
+      if (lane >= off) v += u;
+    }
+    incl[d] = v;
+  }
+  if (lane == 63)
+#pragma unroll
+    for (int d = 0; d < kBuckets; ++d) wtot[w][d] = incl[d];
   __syncthreads();
   if (t < kBuckets) {
-    // exclusive scan over threads for bucket t
     int64_t run = 0;
-    for (int k = 0; k < kScanThreads; ++k) {
-      const int64_t v = part[k][t];
-      part[k][t] = run;
+    for (int k = 0; k < NWAVE; ++k) {
+      const int64_t v = wtot[k][t];
+      wtot[k][t] = run;
       run += v;
     }
     plan->count[t] = run;
@@ -211,8 +328,10 @@ __device__ __forceinline__ void scan_body(int32_t* __restrict__ counts, int64_t 
   }
   __syncthreads();
   int64_t run[kBuckets];
-  for (int d = 0; d < kBuckets; ++d) run[d] = start[d] + part[t][d];
-  for (int64_t b = b0; b < b1; ++b)
+#pragma unroll
+  for (int d = 0; d < kBuckets; ++d) run[d] = start[d] + wtot[w][d] + incl[d] - sum[d];
+  for (b = b0; b < b1; ++b)
+#pragma unroll
     for (int d = 0; d < kBuckets; ++d) {
       const int32_t c = counts[b * kBuckets + d];
       counts[b * kBuckets + d] = (int32_t)run[d];
@@ -226,46 +345,123 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int32_t* __restrict__ cou
   scan_body(counts, nblk, L, tile_q, plan);
 }
 
+// Large queries scan in three launches: per-group sums of kScanGroup
+// chunks (many workgroups), the scan of the group sums (one workgroup, as
+// above), then each group's chunk offsets from its group offset.
+__global__ __launch_bounds__(64) void k_group_sums(const int32_t* __restrict__ counts,
+                                                   int64_t nblk, int32_t* __restrict__ groups) {
+  const int d = threadIdx.x;
+  if (d >= kBuckets) return;
+  const int64_t b0 = (int64_t)blockIdx.x * kScanGroup;
+  const int64_t b1 = b0 + kScanGroup < nblk ? b0 + kScanGroup : nblk;
+  int32_t sum = 0;
+  for (int64_t b = b0; b < b1; ++b) sum += counts[b * kBuckets + d];
+  groups[(int64_t)blockIdx.x * kBuckets + d] = sum;
+}
+
+__global__ __launch_bounds__(64) void k_group_offsets(int32_t* __restrict__ counts, int64_t nblk,
+                                                      const int32_t* __restrict__ groups) {
+  const int d = threadIdx.x;
+  if (d >= kBuckets) return;
+  const int64_t b0 = (int64_t)blockIdx.x * kScanGroup;
+  const int64_t b1 = b0 + kScanGroup < nblk ? b0 + kScanGroup : nblk;
+  int32_t c[kScanGroup];
+#pragma unroll
+  for (int k = 0; k < kScanGroup; ++k) c[k] = b0 + k < b1 ? counts[(b0 + k) * kBuckets + d] : 0;
+  int32_t run = groups[(int64_t)blockIdx.x * kBuckets + d];
+#pragma unroll
+  for (int k = 0; k < kScanGroup; ++k)
+    if (b0 + k < b1) {
+      counts[(b0 + k) * kBuckets + d] = run;
+      run += c[k];
+    }
+}
+
+// Scatter of one lookup block's points into the permutation, stable within
+// each depth bucket. A thread takes kPP consecutive points per round. Within
+// a wavefront a point's rank among equal depths is the count of such points
+// in lower lanes (one ballot per slot) plus those in its own lane's earlier
+// slots; the per-(round, wavefront) bucket counts are then turned into
+// offsets by one pass over the block, in point order.
 __device__ __forceinline__ void scatter_block(int64_t blk, const uint8_t* __restrict__ depth,
                                               int64_t n, const int32_t* __restrict__ offs,
                                               int32_t* __restrict__ perm) {
-  __shared__ int run[kBuckets];
-  __shared__ int wcnt[kLookupThreads / 64][kBuckets];
+  constexpr int NWV = kLookupThreads / 64;
+  __shared__ int wcnt[kQuadRounds][NWV][kBuckets];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t base = blk * kLookupChunk;
-  if (t < kBuckets) run[t] = offs[blk * kBuckets + t];
-  for (int r = 0; r < kRounds; ++r) {
-    const int64_t q0 = base + (int64_t)r * kLookupThreads;
-    if (q0 >= n) break;
-    __syncthreads();  // the previous round's update of run[] has read wcnt
-    if (t < kBuckets * (kLookupThreads / 64)) wcnt[t / kBuckets][t % kBuckets] = 0;
-    __syncthreads();
-    const int64_t q = q0 + t;
-    const int d = q < n ? depth[q] : 0;
-    const bool valid = q < n && d > 0;
-    // rank among equal depths within the wavefront
-    uint64_t todo = __ballot(valid);
-    int rank = 0;
-    while (todo) {
-      const int leader = __ffsll((unsigned long long)todo) - 1;
-      const int v = __shfl(d, leader);
-      const uint64_t m = __ballot(valid && d == v);
-      if (valid && d == v) rank = __popcll(m & lanemask_lt());
-      if (lane == leader) wcnt[w][v] = __popcll(m);
-      todo &= ~m;
+  for (int i = t; i < kQuadRounds * NWV * kBuckets; i += kLookupThreads) (&wcnt[0][0][0])[i] = 0;
+  const bool vec = ((uintptr_t)depth & 3) == 0;
+  int d[kQuadRounds][kPP], rank[kQuadRounds][kPP];
+#pragma unroll
+  for (int r = 0; r < kQuadRounds; ++r) {
+    const int64_t q0 = base + ((int64_t)r * kLookupThreads + t) * kPP;
+    if (vec && q0 + kPP <= n) {
+      const uint32_t v = *(const uint32_t*)(depth + q0);
+#pragma unroll
+      for (int j = 0; j < kPP; ++j) d[r][j] = (v >> (8 * j)) & 0xff;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kPP; ++j) d[r][j] = q0 + j < n ? depth[q0 + j] : 0;
     }
-    __syncthreads();
-    if (valid) {
-      int pos = run[d] + rank;
-      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      perm[pos] = (int32_t)q;
+  }
+  __syncthreads();   // wcnt cleared
+  const uint64_t lt = lanemask_lt();
+#pragma unroll
+  for (int r = 0; r < kQuadRounds; ++r) {
+    bool todo[kPP];
+#pragma unroll
+    for (int j = 0; j < kPP; ++j) {
+      todo[j] = d[r][j] > 0;   // invalid points read as depth 0
+      rank[r][j] = 0;
     }
-    __syncthreads();
-    if (t < kBuckets) {
-      int add = 0;
-      for (int k = 0; k < kLookupThreads / 64; ++k) add += wcnt[k][t];
-      run[t] += add;
+    for (;;) {
+      bool mine_any = false;
+      int mine = 0;
+#pragma unroll
+      for (int j = kPP - 1; j >= 0; --j)
+        if (todo[j]) {
+          mine_any = true;
+          mine = d[r][j];
+        }
+      const uint64_t any = __ballot(mine_any);
+      if (!any) break;
+      const int leader = __ffsll((unsigned long long)any) - 1;
+      const int v = __shfl(mine, leader);
+      int below = 0, total = 0, own = 0;
+#pragma unroll
+      for (int j = 0; j < kPP; ++j) {
+        const uint64_t m = __ballot(d[r][j] == v);
+        below += __popcll(m & lt);
+        total += __popcll(m);
+      }
+#pragma unroll
+      for (int j = 0; j < kPP; ++j)
+        if (d[r][j] == v) {
+          rank[r][j] = below + own;
+          ++own;
+          todo[j] = false;
+        }
+      if (lane == leader) wcnt[r][w][v] = total;
     }
+  }
+  __syncthreads();
+  if (t < kBuckets) {
+    int run = offs[blk * kBuckets + t];
+    for (int r = 0; r < kQuadRounds; ++r)
+      for (int k = 0; k < NWV; ++k) {
+        const int c = wcnt[r][k][t];
+        wcnt[r][k][t] = run;
+        run += c;
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kQuadRounds; ++r) {
+    const int64_t q0 = base + ((int64_t)r * kLookupThreads + t) * kPP;
+#pragma unroll
+    for (int j = 0; j < kPP; ++j)
+      if (d[r][j] > 0) perm[wcnt[r][w][d[r][j]] + rank[r][j]] = (int32_t)(q0 + j);
   }
 }
 
@@ -339,9 +535,17 @@ hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map, 
 }
 
 hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q, Plan* plan,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, nblk, L, tile_q,
-                     plan);
+                       int32_t* groups, hipStream_t s) {
+  if (nblk <= kScanThreads) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, nblk, L, tile_q,
+                       plan);
+    return hipGetLastError();
+  }
+  const int64_t ngrp = (nblk + kScanGroup - 1) / kScanGroup;
+  hipLaunchKernelGGL(k_group_sums, dim3((unsigned)ngrp), dim3(64), 0, s, counts, nblk, groups);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, groups, ngrp, L, tile_q, plan);
+  hipLaunchKernelGGL(k_group_offsets, dim3((unsigned)ngrp), dim3(64), 0, s, counts, nblk,
+                     groups);
   return hipGetLastError();
 }
 

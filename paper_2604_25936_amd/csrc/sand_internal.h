@@ -39,6 +39,7 @@ constexpr int kMaxWidth = 352;
 constexpr int kBuckets = kMaxLayers + 1;   // exit depths 0..16
 constexpr int kLookupThreads = 256;
 constexpr int kLookupChunk = 4096;         // points per lookup block
+constexpr int kScanGroup = 32;             // lookup blocks per group of the large-query scan
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
@@ -152,8 +153,10 @@ hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map,
                                const uint8_t* forced,
                                int mode, int L, int max_depth, uint8_t* depth,
                                float* sdf, float* grad, int32_t* counts, hipStream_t s);
+// groups: scratch of ceil(nblk / kScanGroup) * kBuckets int32, used when
+// nblk exceeds one scan workgroup's threads
 hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q,
-                       Plan* plan, hipStream_t s);
+                       Plan* plan, int32_t* groups, hipStream_t s);
 hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
                           int32_t* perm, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
