@@ -537,16 +537,21 @@ def main():
         comparisons["speedup_adaptive_bf16_vs_full_fp32"] = \
             comparisons["full_fp32"]["ms_per_step"] / (t_step * 1e3)
         # map-free dynamic early exit on |t_j| < r (the Sec. 4.4 ablation), r = 1.5e-4
+        # (checkpoint 0: the library picks the compaction layer from a sample;
+        # -1: no compaction, a tile runs as deep as its deepest point)
         for prec in ("bf16", "fp32"):
             log(f"comparison: dynamic early exit without a map, {prec}")
-            dyn = lambda p=prec: sand.query(model, None, xyz, out=sdf, precision=p,
-                                            mode="dynamic", dynamic_r=1.5e-4, depth_out=depth)
-            t = time_steps(dyn, 2, 1)
+            res = {"r": 1.5e-4}
+            for name, cp in (("compacted", 0), ("uncompacted", -1)):
+                dyn = lambda p=prec, c=cp: sand.query(model, None, xyz, out=sdf, precision=p,
+                                                      mode="dynamic", dynamic_r=1.5e-4,
+                                                      depth_out=depth, dynamic_checkpoint=c)
+                t = time_steps(dyn, 2, 1)
+                res[name] = {"queries_per_s": n / t, "ms_per_step": t * 1e3}
             dh = torch.bincount(depth.to(torch.int64), minlength=L + 1).cpu().numpy()
-            comparisons[f"dynamic_{prec}"] = {
-                "queries_per_s": n / t, "ms_per_step": t * 1e3, "r": 1.5e-4,
-                "exit_histogram": [int(c) for c in dh],
-                "hidden_mfma_flop_algorithmic": hidden_flops(dh, W)}
+            res["exit_histogram"] = [int(c) for c in dh]
+            res["hidden_mfma_flop_algorithmic"] = hidden_flops(dh, W)
+            comparisons[f"dynamic_{prec}"] = res
         # restore the headline's depths for anything after
         sand.query(model, dm, xyz, out=sdf, precision="bf16", depth_out=depth, workspace=ws)
         # plain PyTorch FP32 of the same model on this GPU (context)

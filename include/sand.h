@@ -82,6 +82,18 @@ typedef struct {
                                    allocates stream-ordered scratch itself) */
   size_t workspace_bytes;       /* size of workspace; must be at least
                                    sand_query_workspace_size(n) when given */
+  int32_t dynamic_checkpoint;   /* DYNAMIC only (else 0): the layer c after
+                                   which points still running leave their
+                                   tiles and continue, from layer c + 1, in
+                                   full tiles of such points (results are
+                                   the same for every c). 0: chosen by the
+                                   library from the exit depths of a 65536-
+                                   point strided sample when n >= 2^22 (one
+                                   host synchronisation); -1: never; values
+                                   >= the exit-depth bound mean never. The
+                                   library allocates the compaction arena
+                                   itself (stream-ordered, at most 2 GiB;
+                                   larger queries run in slabs). */
 } sand_query_opts;
 
 /* Fill opts with the defaults: FP32, ADAPTIVE, no clamp, no buffers. */

@@ -915,8 +915,12 @@ sand_status check_query(const char* who, sand_model m, sand_depthmap dm, const f
   if (o.mode == SAND_DYNAMIC) {
     if (!(o.dynamic_r > 0.0f) || !std::isfinite(o.dynamic_r))
       return fail(SAND_ERR_INVALID, "%s: dynamic mode needs a finite dynamic_r > 0", who);
-  } else if (o.dynamic_r != 0.0f) {
-    return fail(SAND_ERR_INVALID, "%s: dynamic_r is only for dynamic mode", who);
+    if (o.dynamic_checkpoint < -1 || o.dynamic_checkpoint == 1)
+      return fail(SAND_ERR_INVALID, "%s: dynamic_checkpoint %d (need -1, 0 or >= 2)", who,
+                  o.dynamic_checkpoint);
+  } else if (o.dynamic_r != 0.0f || o.dynamic_checkpoint != 0) {
+    return fail(SAND_ERR_INVALID, "%s: dynamic_r and dynamic_checkpoint are only for dynamic mode",
+                who);
   }
   if (dm && dm->model != m) return fail(SAND_ERR_INVALID, "%s: map belongs to another model", who);
   if (o.mode == SAND_ADAPTIVE && !dm) return fail(SAND_ERR_INVALID, "%s: adaptive mode needs a map", who);
@@ -967,6 +971,98 @@ sand_status run_bucketing(sand_model m, sand_depthmap dm, const float* xyz, int6
 }
 
 // Lookup + bucketing + T-MLP for n points. `ws` must hold workspace_layout(n).
+namespace {
+
+constexpr int64_t kDynSampleMin = int64_t(1) << 22;   // queries that pick their own checkpoint
+constexpr int64_t kDynSample = 65536;                 // points in the sample
+constexpr size_t kDynArenaBytes = size_t(1) << 31;    // compaction arena limit
+
+// Checkpoint layer for compacted dynamic exit, from the exit depths of a
+// strided sample of the query: with s_c the fraction of points still
+// running after layer c, compaction at c costs about (c - 1) + s_c (a + d -
+// c) hidden-layer evaluations per point against d - 1 without (a tile runs
+// as deep as its deepest point); a is the cost of writing and reading back
+// a record, in hidden-layer evaluations. Returns -1 when compaction does not
+// pay.
+int choose_checkpoint(sand_model m, int prec, const float* xyz, int64_t n, int d, float r,
+                      hipStream_t s, sand_status& st) {
+  st = SAND_OK;
+  if (n < kDynSampleMin || d < 4) return -1;
+  const int64_t ns = kDynSample, stride = n / ns;
+  char* tmp = nullptr;
+  if (hipMallocAsync((void**)&tmp, (size_t)ns * 17, s) != hipSuccess) return -1;
+  float* sx = (float*)tmp;
+  float* sy = sx + 3 * ns;
+  uint8_t* sd = (uint8_t*)(sy + ns);
+  QueryArgs qa{};
+  qa.m = m->args[prec];
+  qa.xyz = sx;
+  qa.sdf = sy;
+  qa.n = ns;
+  qa.full_depth = d;
+  qa.dyn_r = r;
+  qa.depth_out = sd;
+  std::vector<uint8_t> h((size_t)ns);
+  hipError_t e = launch_gather_points(xyz, stride, ns, sx, s);
+  if (e == hipSuccess) e = launch_tmlp(prec, qa, m->num_cu, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), sd, (size_t)ns, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFreeAsync(tmp, s);
+  if (e != hipSuccess) {
+    st = device_fail(e, "dynamic checkpoint sample");
+    return -1;
+  }
+  std::vector<int64_t> hist(kBuckets, 0);
+  for (uint8_t v : h) ++hist[v < kBuckets ? v : kBuckets - 1];
+  const double a = prec == PREC_FP32 ? 0.4 : 1.7;
+  double best = (double)(d - 1);
+  int bc = -1;
+  int64_t running = ns;
+  for (int c = 1; c < d; ++c) {
+    running -= hist[c];
+    if (c < 2) continue;
+    const double cost = (c - 1) + (double)running / ns * (a + d - c);
+    if (cost < 0.95 * best) {
+      best = cost;
+      bc = c;
+    }
+  }
+  return bc;
+}
+
+// Dynamic exit with compaction after layer cp: per slab of at most `cap`
+// points (the records the arena holds), the spilling launch, then the
+// resumed tiles of its records.
+sand_status run_dynamic_compacted(sand_model m, int prec, const QueryArgs& base, int cp,
+                                  hipStream_t s) {
+  const int64_t rec = dyn_record_bytes(prec, m->WP);
+  int64_t cap = (int64_t)(kDynArenaBytes / (size_t)rec);
+  if (cap > base.n) cap = base.n;
+  char* arena = nullptr;
+  if (hipMallocAsync((void**)&arena, 256 + (size_t)cap * rec, s) != hipSuccess)
+    return fail(SAND_ERR_NOMEM, "sand_query: compaction arena of %lld bytes",
+                (long long)(256 + cap * rec));
+  hipError_t e = hipSuccess;
+  for (int64_t s0 = 0; s0 < base.n && e == hipSuccess; s0 += cap) {
+    QueryArgs qa = base;
+    qa.xyz = base.xyz + 3 * s0;
+    qa.sdf = base.sdf + s0;
+    qa.n = base.n - s0 < cap ? base.n - s0 : cap;
+    if (base.depth_out) qa.depth_out = base.depth_out + s0;
+    qa.spill.arena = arena + 256;
+    qa.spill.count = (int*)arena;
+    qa.spill.cap = cap;
+    qa.spill.layer = cp;
+    e = launch_fill_u8((uint8_t*)arena, 4, 0, s);
+    if (e == hipSuccess) e = launch_tmlp(prec, qa, m->num_cu, s);
+    if (e == hipSuccess) e = launch_tmlp_resume(prec, qa, m->num_cu, s);
+  }
+  (void)hipFreeAsync(arena, s);
+  return e == hipSuccess ? SAND_OK : device_fail(e, "compacted dynamic launch");
+}
+
+}  // namespace
+
 sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_t n, float* sdf,
                         const sand_query_opts& o, char* ws, hipStream_t s, hipEvent_t* ev) {
   auto mark = [&](int i) {
@@ -985,8 +1081,21 @@ sand_status run_forward(sand_model m, sand_depthmap dm, const float* xyz, int64_
     if (o.mode == SAND_DYNAMIC) {
       qa.dyn_r = o.dynamic_r;
       qa.depth_out = o.depth_out;
+      for (int i = 0; i < 4; ++i) mark(i);   // the checkpoint sample counts as t-mlp time
+      int cp = o.dynamic_checkpoint;
+      if (cp == 0) {
+        sand_status st = SAND_OK;
+        cp = choose_checkpoint(m, prec, xyz, n, d, o.dynamic_r, s, st);
+        if (st != SAND_OK) return st;
+      }
+      if (cp >= 2 && cp < d) {
+        const sand_status st = run_dynamic_compacted(m, prec, qa, cp, s);
+        mark(4);
+        return st;
+      }
+    } else {
+      for (int i = 0; i < 4; ++i) mark(i);
     }
-    for (int i = 0; i < 4; ++i) mark(i);
     if ((e = launch_tmlp(prec, qa, m->num_cu, s)) != hipSuccess) return device_fail(e, "t-mlp launch");
     mark(4);
     if (o.mode == SAND_FULL && o.depth_out &&

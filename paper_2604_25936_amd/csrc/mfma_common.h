@@ -169,6 +169,10 @@ struct Cfg {
   static constexpr int Q = NW * T::NQ;          // points per tile
   static constexpr int RB = WP / T::BM;         // output blocks per layer
   static constexpr int KS = RB * T::SPB;        // K steps of a hidden product
+  // compacted dynamic exit: a point's record is a 16-byte header (index, y)
+  // and the packed layer output held by its GL lanes, KS vectors each
+  static constexpr int GL = 64 / T::NQ;
+  static constexpr int REC = 16 + GL * KS * T::VB;
   // forward chunk: KS weight steps + 1 bias step, then tail weights
   static constexpr int TAIL_OFF = (KS + 1) * 64 * T::VB;
   static constexpr int CH = TAIL_OFF + T::TAILB;

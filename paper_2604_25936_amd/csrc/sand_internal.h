@@ -94,6 +94,17 @@ struct Plan {
   int32_t pad;
 };
 
+// Compaction of map-free dynamic exit: points still running after layer
+// `layer` leave their tile as records (point index, y, the packed layer
+// output) in `arena`, and a second launch runs them on from layer + 1 in
+// full tiles. Record r occupies dyn_record_bytes() bytes at arena + r * that.
+struct DynSpill {
+  char* arena;
+  int* count;              // records written by the spilling launch
+  int64_t cap;             // records the arena holds
+  int layer;               // 0: no compaction
+};
+
 // Everything one forward launch needs.
 struct QueryArgs {
   ModelArgs m;
@@ -106,6 +117,7 @@ struct QueryArgs {
   float* y_all;            // [n][L] every accumulated output y_1..y_d, or null
   float dyn_r;             // > 0: map-free early exit on |t_j| < dyn_r (j >= 2)
   uint8_t* depth_out;      // [n] exit depths (written when dyn_r > 0), or null
+  DynSpill spill;          // dynamic mode: spill after spill.layer (0: none)
 };
 
 // One query of a batched launch (server). Pointers are device memory; the
@@ -195,5 +207,13 @@ int adjoint_tile_points(int prec);   // adjoint tile (the plan's tile_q for sand
 size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L);
 hipError_t launch_adjoint(int prec, const AdjointArgs& a, int grid, hipStream_t s);
 hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s);
+// Second launch of compacted dynamic exit: the records of a.spill, from
+// layer a.spill.layer + 1 on (a.xyz unused; a.sdf/a.depth_out indexed as in
+// the spilling launch).
+hipError_t launch_tmlp_resume(int prec, const QueryArgs& a, int num_cu, hipStream_t s);
+int dyn_record_bytes(int prec, int WP);
+// out[i] = xyz[i * stride] for i < n (float3 points).
+hipError_t launch_gather_points(const float* xyz, int64_t stride, int64_t n, float* out,
+                                hipStream_t s);
 
 }  // namespace sand

@@ -35,6 +35,8 @@
 // The grid is persistent and strides over tiles, which the plan orders
 // deepest bucket first.
 
+#include <type_traits>
+
 #include "mfma_common.h"
 
 #ifndef SAND_APF
@@ -406,6 +408,60 @@ __device__ __forceinline__ void decode_tile(const Plan* plan, int L, int64_t til
   if (cnt > Q) cnt = Q;
 }
 
+// Hidden layers j0..d of a tile. Layer j reads actA and writes actB when j
+// is even, the reverse when it is odd (layer 1 writes actA). `after(j, y_j,
+// t_j, out)` sees each layer's output (out: its packed activations) and
+// returns false to stop the tile. ODD_START: j0 is odd (a resumed tile).
+template <int PREC, int WP, bool ODD_START, class After>
+__device__ __forceinline__ void run_layers(const ModelArgs& M, int j0, int d, float y,
+                                           const char* hidden, char* ring, int wave, int lane,
+                                           int g, int& c, int nc,
+                                           typename Tr<PREC>::V (&actA)[Cfg<PREC, WP>::KS],
+                                           typename Tr<PREC>::V (&actB)[Cfg<PREC, WP>::KS],
+                                           After after) {
+  using V = typename Tr<PREC>::V;
+  constexpr int KS = Cfg<PREC, WP>::KS;
+  // layers j0, j0 + 2, ... read `p` and write `q`; the others the reverse
+  V (&p)[KS] = ODD_START ? actB : actA;
+  V (&q)[KS] = ODD_START ? actA : actB;
+  float t;
+  for (int j = j0; j <= d; j += 2) {
+    y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, p, q, M.c0[j - 1],
+                               M.c1[j - 1], t);
+    if (!after(j, y, t, q) || j + 1 > d) break;
+    y = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, q, p, M.c0[j], M.c1[j], t);
+    if (!after(j + 1, y, t, p)) break;
+  }
+}
+
+// Write the records of this wavefront's points that are still running after
+// layer j (spill arena of compacted dynamic exit); `out` holds layer j's
+// packed output. One atomic per wavefront reserves the records.
+template <int PREC, int WP>
+__device__ __forceinline__ void spill_points(const DynSpill& sp, bool running, int gi, float y,
+                                             int lane, int g,
+                                             const typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS]) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  const int col = T::col(lane);
+  const uint64_t m = __ballot(running && g == 0);   // group-0 lanes are columns 0..NQ-1
+  int base = 0;
+  if (lane == 0 && m != 0ull) base = atomicAdd(sp.count, __popcll(m));
+  base = __shfl(base, 0);
+  const int rank = __popcll(m & (col == 0 ? 0ull : (~0ull >> (64 - col))));
+  const int64_t r = (int64_t)base + rank;
+  if (!running || r >= sp.cap) return;
+  char* rec = sp.arena + r * C::REC;
+  if (g == 0) {
+    ((int*)rec)[0] = gi;
+    ((float*)rec)[1] = y;
+  }
+  V* dst = (V*)(rec + 16 + g * C::KS * T::VB);
+#pragma unroll
+  for (int s = 0; s < C::KS; ++s) dst[s] = out[s];
+}
+
 // Evaluate one tile of exit depth d. This lane's point is gi (< 0: none)
 // at (px, py, pz); every lane of the same column holds the same point.
 template <int PREC, int WP>
@@ -413,7 +469,7 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
                                          int gi, float px, float py, float pz, char* ring,
                                          const char* l1, int lane, int wave,
                                          float* __restrict__ y_all, float dyn_r,
-                                         uint8_t* __restrict__ depth_out) {
+                                         uint8_t* __restrict__ depth_out, const DynSpill& sp) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
@@ -451,10 +507,12 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
   }
   // Map-free early exit (dyn_r > 0): a point's output is frozen after the
   // first layer j >= 2 whose tail t_j is below dyn_r in magnitude; the
-  // workgroup stops once none of its points is still running.
-  bool alive = ok;
+  // workgroup stops once none of its points is still running. With
+  // compaction (sp.layer), the points still running after layer sp.layer
+  // leave as records and the tile stops.
+  bool alive = ok, spilled = false;
   int dexit = d;
-  auto after_layer = [&](int j, float yn, float t) {
+  auto after_layer = [&](int j, float yn, float t, const V (&out)[C::KS]) {
     if (dyn_r > 0.0f) {
       if (alive) {
         y = yn;
@@ -463,25 +521,92 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
           dexit = j;
         }
       }
+      if (j == sp.layer && j < d) {
+        spill_points<PREC, WP>(sp, alive, gi, y, lane, g, out);
+        spilled = alive;
+        alive = false;
+        return false;
+      }
       return __syncthreads_or(alive ? 1 : 0) != 0;
     }
     y = yn;
     if (yrow) yrow[j - 1] = y;
     return true;
   };
-  for (int j = 2; j <= d; j += 2) {
-    float t;
-    float yn = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actA, actB,
-                                      M.c0[j - 1], M.c1[j - 1], t);
-    if (!after_layer(j, yn, t) || j + 1 > d) break;
-    yn = hidden_layer<PREC, WP>(y, hidden, ring, wave, lane, g, c, nc, actB, actA, M.c0[j],
-                                M.c1[j], t);
-    if (!after_layer(j + 1, yn, t)) break;
-  }
-  if (depth_out && g == 0 && ok) depth_out[gi] = (uint8_t)(dyn_r > 0.0f ? dexit : d);
+  run_layers<PREC, WP, false>(M, 2, d, y, hidden, ring, wave, lane, g, c, nc, actA, actB,
+                              after_layer);
+  const bool done = ok && !spilled;
+  if (depth_out && g == 0 && done) depth_out[gi] = (uint8_t)(dyn_r > 0.0f ? dexit : d);
   // the last epilogue read a ring slot the next tile's first load may reuse,
   // and an early exit can leave chunk copies in flight
   if (nc > 0) {
+    wait_chunk();
+    __syncthreads();
+  }
+  if (g == 0 && done) sdf[gi] = y;
+}
+
+// A resumed tile of compacted dynamic exit: up to Q records, each run from
+// layer j0 = spill layer + 1 to d with the exit test. This lane's record is
+// ri (< 0: none). ODD: j0 is odd.
+template <int PREC, int WP, bool ODD>
+__device__ __forceinline__ void resume_tile(const ModelArgs& M, float* __restrict__ sdf, int d,
+                                            const DynSpill& sp, int ri, char* ring, int lane,
+                                            int wave, float dyn_r,
+                                            uint8_t* __restrict__ depth_out) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  const int g = T::grp(lane);
+  const char* hidden = M.chunks + C::L1B;
+  const int j0 = sp.layer + 1;
+  V actA[C::KS], actB[C::KS];
+  int gi = -1;
+  float y = 0.0f;
+  const char* rec = sp.arena + (int64_t)(ri < 0 ? 0 : ri) * C::REC;
+  const V* src = (const V*)(rec + 16 + g * C::KS * T::VB);
+  if (ri >= 0) {
+    gi = ((const int*)rec)[0];
+    y = ((const float*)rec)[1];
+  }
+  const bool ok = gi >= 0;
+  // chunks of layers j0..d: absolute chunk indices c0 .. nc-1, chunk c in
+  // ring slot c % NSLOT as in run_tile
+  const int c0 = (j0 - 2) * C::RB, nc = (d - 1) * C::RB;
+  int c = c0;
+#pragma unroll
+  for (int k = 0; k < C::PD; ++k)
+    if (c0 + k < nc)
+      load_chunk<C::CH, C::NWF>(hidden + (size_t)(c0 + k) * C::CH,
+                                ring + ((c0 + k) % C::NSLOT) * C::CH, wave, lane);
+  if (c0 < nc) {
+    const int lpc = chunk_loads<C::CH, C::NWF>(wave);
+    int later = 0;
+#pragma unroll
+    for (int k = 1; k < C::PD; ++k) later += (c0 + k < nc) ? lpc : 0;
+    wait_vm(later);
+    __syncthreads();
+  }
+  bool alive = ok;
+  int dexit = d;
+  auto after_layer = [&](int j, float yn, float t, const V (&)[C::KS]) {
+    if (alive) {
+      y = yn;
+      if (fabsf(t) < dyn_r) {
+        alive = false;
+        dexit = j;
+      }
+    }
+    return __syncthreads_or(alive ? 1 : 0) != 0;
+  };
+  // the record's activations are layer j0's input: actB when j0 is odd
+  V (&in)[C::KS] = ODD ? actB : actA;
+#pragma unroll
+  for (int s = 0; s < C::KS; ++s) in[s] = ri >= 0 ? src[s] : V{};
+  run_layers<PREC, WP, ODD>(M, j0, d, y, hidden, ring, wave, lane, g, c, nc, actA, actB,
+                            after_layer);
+  if (depth_out && g == 0 && ok) depth_out[gi] = (uint8_t)dexit;
+  if (c0 < nc) {
     wait_chunk();
     __syncthreads();
   }
@@ -566,7 +691,7 @@ void k_tmlp(QueryArgs a) {
     float nx, ny, nz;
     point_coords(a.xyz, gi_next, nx, ny, nz);
     run_tile<PREC, WP>(a.m, a.sdf, d, gi, px, py, pz, ring, l1, lane, wave, a.y_all, a.dyn_r,
-                       a.depth_out);
+                       a.depth_out, a.spill);
     d = d_next;
     gi = gi_next;
     px = nx;
@@ -613,8 +738,40 @@ void k_tmlp_batch(BatchArgs a) {
     float px, py, pz;
     point_coords(q.xyz, gi, px, py, pz);
     run_tile<PREC, WP>(M, q.sdf, d, gi, px, py, pz, ring, l1, lane, wave, nullptr, 0.0f,
-                       nullptr);
+                       nullptr, DynSpill{});
   }
+}
+
+// Second launch of compacted dynamic exit: persistent over the tiles of the
+// records the spilling launch wrote (their count is read on the device).
+template <int PREC, int WP, bool ODD>
+__global__ __launch_bounds__((Cfg<PREC, WP>::NTF)) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_tmlp_resume(QueryArgs a) {
+  using C = Cfg<PREC, WP>;
+  using T = Tr<PREC>;
+  constexpr int Q = C::QF;
+  __shared__ __attribute__((aligned(16))) char ring[C::NSLOT * C::CH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int64_t count = *a.spill.count;
+  if (count > a.spill.cap) count = a.spill.cap;
+  const int64_t total = (count + Q - 1) / Q;
+  const int qi = wave * T::NQ + T::col(lane);
+  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int64_t ri = tile * Q + qi;
+    resume_tile<PREC, WP, ODD>(a.m, a.sdf, a.full_depth, a.spill, ri < count ? (int)ri : -1,
+                               ring, lane, wave, a.dyn_r, a.depth_out);
+  }
+}
+
+// Points xyz[i * stride], i < n, gathered into out (a sample of a query).
+__global__ void k_gather_points(const float* __restrict__ xyz, int64_t stride, int64_t n,
+                                float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* p = xyz + 3 * (i * stride);
+  out[3 * i] = p[0];
+  out[3 * i + 1] = p[1];
+  out[3 * i + 2] = p[2];
 }
 
 template <int PREC, int WP>
@@ -628,6 +785,29 @@ hipError_t launch_one(const QueryArgs& a, int num_cu, hipStream_t s) {
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL((k_tmlp<PREC, WP>), dim3((unsigned)grid), dim3(C::NTF), 0, s, a);
   return hipGetLastError();
+}
+
+template <int PREC, int WP>
+hipError_t launch_resume_one(const QueryArgs& a, int num_cu, hipStream_t s) {
+  using C = Cfg<PREC, WP>;
+  if ((a.spill.layer + 1) & 1)
+    hipLaunchKernelGGL((k_tmlp_resume<PREC, WP, true>), dim3((unsigned)(num_cu * C::WGF)),
+                       dim3(C::NTF), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_tmlp_resume<PREC, WP, false>), dim3((unsigned)(num_cu * C::WGF)),
+                       dim3(C::NTF), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_resume_prec(const QueryArgs& a, int num_cu, hipStream_t s) {
+  switch (a.m.WP) {
+    case 64: return launch_resume_one<PREC, 64>(a, num_cu, s);
+    case 128: return launch_resume_one<PREC, 128>(a, num_cu, s);
+    case 256: return launch_resume_one<PREC, 256>(a, num_cu, s);
+    case 352: return launch_resume_one<PREC, 352>(a, num_cu, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int PREC>
@@ -671,6 +851,35 @@ hipError_t launch_tmlp_batch(int prec, int WP, const BatchArgs& a, int num_cu, h
   if (prec == PREC_FP32) return launch_batch_prec<PREC_FP32>(WP, a, num_cu, s);
   if (prec == PREC_BF16) return launch_batch_prec<PREC_BF16>(WP, a, num_cu, s);
   return launch_batch_prec<PREC_FP16>(WP, a, num_cu, s);
+}
+
+hipError_t launch_tmlp_resume(int prec, const QueryArgs& a, int num_cu, hipStream_t s) {
+  if (prec == PREC_FP32) return launch_resume_prec<PREC_FP32>(a, num_cu, s);
+  if (prec == PREC_BF16) return launch_resume_prec<PREC_BF16>(a, num_cu, s);
+  return launch_resume_prec<PREC_FP16>(a, num_cu, s);
+}
+
+int dyn_record_bytes(int prec, int WP) {
+  auto pick = [&](auto tag) -> int {
+    constexpr int P = decltype(tag)::value;
+    switch (WP) {
+      case 64: return Cfg<P, 64>::REC;
+      case 128: return Cfg<P, 128>::REC;
+      case 256: return Cfg<P, 256>::REC;
+      default: return Cfg<P, 352>::REC;
+    }
+  };
+  if (prec == PREC_FP32) return pick(std::integral_constant<int, PREC_FP32>{});
+  if (prec == PREC_BF16) return pick(std::integral_constant<int, PREC_BF16>{});
+  return pick(std::integral_constant<int, PREC_FP16>{});
+}
+
+hipError_t launch_gather_points(const float* xyz, int64_t stride, int64_t n, float* out,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xyz,
+                     stride, n, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s) {

@@ -29,7 +29,8 @@ class QueryOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("max_depth", ctypes.c_int32), ("dynamic_r", ctypes.c_float),
                 ("forced_depth", ctypes.c_void_p), ("depth_out", ctypes.c_void_p),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("dynamic_checkpoint", ctypes.c_int32)]
 
 
 class ServerInfo(ctypes.Structure):
@@ -246,10 +247,12 @@ def query_grad_workspace_size(model, n, precision="fp32"):
     return int(library().sand_query_grad_workspace_size(model.handle, int(n), p))
 
 
-def _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r=0.0):
+def _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r=0.0,
+          dynamic_checkpoint=0):
     o = QueryOpts()
     library().sand_query_opts_init(ctypes.byref(o))
     o.dynamic_r = float(dynamic_r)
+    o.dynamic_checkpoint = int(dynamic_checkpoint)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.max_depth = int(max_depth)
@@ -270,22 +273,27 @@ def _check_points(xyz):
 
 
 def query(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_depth=0,
-          forced_depth=None, depth_out=None, workspace=None, stream=None, dynamic_r=0.0):
+          forced_depth=None, depth_out=None, workspace=None, stream=None, dynamic_r=0.0,
+          dynamic_checkpoint=0):
     """Signed distances of points ``xyz`` (float32 [n, 3] on the model's GPU).
-    mode "dynamic" needs no map and takes the residual threshold dynamic_r."""
+    mode "dynamic" needs no map and takes the residual threshold dynamic_r;
+    dynamic_checkpoint: layer after which running points are compacted (0:
+    chosen by the library, -1: never)."""
     import torch
     _check_points(xyz)
     n = xyz.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xyz.device)
-    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r,
+              dynamic_checkpoint)
     _check(library().sand_query(model.handle, None if dmap is None else dmap.handle, _ptr(xyz), n,
                                 _ptr(out), ctypes.byref(o), _stream(stream)))
     return out
 
 
 def query_timed(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_depth=0,
-                forced_depth=None, depth_out=None, workspace=None, stream=None, dynamic_r=0.0):
+                forced_depth=None, depth_out=None, workspace=None, stream=None, dynamic_r=0.0,
+                dynamic_checkpoint=0):
     """query() that waits and returns (out, phase_ms): device milliseconds of
     [lookup, scan, scatter, t-mlp, whole query] measured with HIP events."""
     import torch
@@ -293,7 +301,8 @@ def query_timed(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", m
     n = xyz.shape[0]
     if out is None:
         out = torch.empty(n, dtype=torch.float32, device=xyz.device)
-    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r,
+              dynamic_checkpoint)
     ms = (ctypes.c_float * 5)()
     _check(library().sand_query_timed(model.handle, None if dmap is None else dmap.handle,
                                       _ptr(xyz), n, _ptr(out), ctypes.byref(o), _stream(stream),
