@@ -843,6 +843,18 @@ extern "C" sand_status sand_construct_octree(sand_model m, int32_t D, int32_t sp
   inf.near_leaves = nnear;
   inf.samples = nsamp;
 
+  // dense index of level K = min(D - 1, 6): most points end in a leaf at or
+  // above it and need one load
+  if (!oa.root_leaf && D >= 2) {
+    const int K = D - 1 < 6 ? D - 1 : 6;
+    uint2* top = nullptr;
+    e = own.get(&top, ((size_t)1 << (3 * K)) * sizeof(uint2), st);
+    if (e == hipSuccess) e = launch_oct_top(oa, K, top, st);
+    if (e != hipSuccess) return bail(e);
+    oa.top = top;
+    oa.top_level = K;
+  }
+
   // the descriptor
   OctreeArgs* oa_d = nullptr;
   e = hipMalloc((void**)&oa_d, sizeof(OctreeArgs));

@@ -63,19 +63,51 @@ __device__ __forceinline__ void octree_leaves(const OctreeArgs& o, const float (
   uint32_t p[P];      // code of the internal node holding the point (level l-1)
   uint64_t w[P];      // the bitmask word holding p's bit
   bool live[P];
-  const uint64_t w0 = o.bits[0][0];
+  const int K = o.top_level;
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     ix[i] = cell_index(x[i], s, half);
     iy[i] = cell_index(y[i], s, half);
     iz[i] = cell_index(z[i], s, half);
-    p[i] = 0;
-    w[i] = w0;
-    live[i] = true;
     d[i] = 0;
     v[i] = __builtin_nanf("");
   }
-  for (int l = 1; l <= D; ++l) {
+  if (K > 0) {
+    // the dense index of level K: the Morton code of the point's level-K cell
+    uint2 e[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      uint32_t code = 0;
+      for (int l = 1; l <= K; ++l) {
+        const int sh = D - l;
+        code = 8u * code + ((((ix[i] >> sh) & 1) << 2) | (((iy[i] >> sh) & 1) << 1) |
+                            ((iz[i] >> sh) & 1));
+      }
+      p[i] = code;
+      e[i] = o.top[code];
+    }
+    const uint64_t* bitsK = o.bits[K];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      live[i] = e[i].x == kOctInternal;
+      w[i] = 0;
+      if (live[i]) {
+        w[i] = bitsK[p[i] >> 6];
+      } else {
+        d[i] = (int)e[i].x;
+        v[i] = __uint_as_float(e[i].y);
+      }
+    }
+  } else {
+    const uint64_t w0 = o.bits[0][0];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      p[i] = 0;
+      w[i] = w0;
+      live[i] = true;
+    }
+  }
+  for (int l = K + 1; l <= D; ++l) {
     bool any = false;
 #pragma unroll
     for (int i = 0; i < P; ++i) any |= live[i];
@@ -154,6 +186,8 @@ __device__ __forceinline__ void lookup_block(
   const int half = R >> 1;
   const float s = (float)half;
   const bool vec_in = ((uintptr_t)xyz & 15) == 0;
+  const bool vec_depth = ((uintptr_t)depth & 3) == 0;
+  const bool vec_sdf = ((uintptr_t)sdf & 15) == 0;
   float pt[kQuadRounds][3 * kPP];
 #pragma unroll
   for (int r = 0; r < kQuadRounds; ++r) {
@@ -214,18 +248,34 @@ __device__ __forceinline__ void lookup_block(
     }
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {
+      if (max_depth > 0 && d[i] > max_depth) d[i] = max_depth;
+      if (q0 + i >= n) d[i] = 0;
+      if (d[i] == 0 && oct == nullptr && far != nullptr && cell[i] >= 0) farv[i] = far[cell[i]];
+    }
+    // whole quads are written with one store each where the pointers allow
+    const bool full = q0 + kPP <= n;
+    if (full && vec_depth) {
+      *(uint32_t*)(depth + q0) = (uint32_t)d[0] | ((uint32_t)d[1] << 8) |
+                                 ((uint32_t)d[2] << 16) | ((uint32_t)d[3] << 24);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kPP; ++i)
+        if (q0 + i < n) depth[q0 + i] = (uint8_t)d[i];
+    }
+    if (sdf) {
+      if (full && vec_sdf && d[0] == 0 && d[1] == 0 && d[2] == 0 && d[3] == 0) {
+        *(float4*)(sdf + q0) = make_float4(farv[0], farv[1], farv[2], farv[3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < kPP; ++i)
+          if (q0 + i < n && d[i] == 0) sdf[q0 + i] = farv[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPP; ++i) {
       const int64_t q = q0 + i;
       const bool valid = q < n;
-      if (max_depth > 0 && d[i] > max_depth) d[i] = max_depth;
-      if (!valid) d[i] = 0;
-      if (valid) {
-        depth[q] = (uint8_t)d[i];
-        if (d[i] == 0) {
-          if (oct == nullptr && far != nullptr && cell[i] >= 0) farv[i] = far[cell[i]];
-          if (sdf) sdf[q] = farv[i];
-          if (grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
-        }
-      }
+      if (valid && d[i] == 0 && grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
       wave_histogram(d[i], valid, hist);
     }
   }
@@ -330,9 +380,11 @@ __device__ __forceinline__ void scan_body(int32_t* __restrict__ counts, int64_t 
   int64_t run[kBuckets];
 #pragma unroll
   for (int d = 0; d < kBuckets; ++d) run[d] = start[d] + wtot[w][d] + incl[d] - sum[d];
+  // bucket 0 is not in the permutation: its entry keeps the chunk's count of
+  // far-field points, which lets the scatter skip chunks without others
   for (b = b0; b < b1; ++b)
 #pragma unroll
-    for (int d = 0; d < kBuckets; ++d) {
+    for (int d = 1; d < kBuckets; ++d) {
       const int32_t c = counts[b * kBuckets + d];
       counts[b * kBuckets + d] = (int32_t)run[d];
       run[d] += c;
@@ -362,7 +414,7 @@ __global__ __launch_bounds__(64) void k_group_sums(const int32_t* __restrict__ c
 __global__ __launch_bounds__(64) void k_group_offsets(int32_t* __restrict__ counts, int64_t nblk,
                                                       const int32_t* __restrict__ groups) {
   const int d = threadIdx.x;
-  if (d >= kBuckets) return;
+  if (d < 1 || d >= kBuckets) return;   // bucket 0 keeps the far-field counts
   const int64_t b0 = (int64_t)blockIdx.x * kScanGroup;
   const int64_t b1 = b0 + kScanGroup < nblk ? b0 + kScanGroup : nblk;
   int32_t c[kScanGroup];
@@ -390,6 +442,9 @@ __device__ __forceinline__ void scatter_block(int64_t blk, const uint8_t* __rest
   __shared__ int wcnt[kQuadRounds][NWV][kBuckets];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t base = blk * kLookupChunk;
+  // offs[.][0] holds the chunk's far-field count: nothing to place if all are far
+  const int64_t in_chunk = n - base < kLookupChunk ? n - base : kLookupChunk;
+  if (offs[blk * kBuckets] >= in_chunk) return;
   for (int i = t; i < kQuadRounds * NWV * kBuckets; i += kLookupThreads) (&wcnt[0][0][0])[i] = 0;
   const bool vec = ((uintptr_t)depth & 3) == 0;
   int d[kQuadRounds][kPP], rank[kQuadRounds][kPP];

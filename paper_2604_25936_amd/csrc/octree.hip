@@ -221,4 +221,44 @@ hipError_t launch_oct_finish(const int32_t* near_slots, int64_t nnear, const uin
   return hipGetLastError();
 }
 
+namespace {
+
+// One thread per level-K cell (Morton code c): the cell's child index at
+// level l is the l-th octal digit of c from the top; descend from the root as
+// the lookup does and record the leaf holding the cell, or that the cell is
+// an internal node.
+__global__ __launch_bounds__(kThreads) void k_oct_top(OctreeArgs o, int K, uint2* __restrict__ top) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ((int64_t)1 << (3 * K))) return;
+  uint64_t p = 0;
+  uint64_t w = o.bits[0][0];
+  for (int l = 1; l <= K; ++l) {
+    const uint64_t child = (uint64_t)(c >> (3 * (K - l))) & 7u;
+    const uint64_t m = 8u * p + child;
+    const uint64_t r = o.rank[l - 1][p >> 6] + (uint64_t)__popcll(w & ((1ull << (p & 63)) - 1ull));
+    const uint64_t slot = 8u * r + child;
+    const uint64_t wn = l < o.D ? o.bits[l][m >> 6] : 0ull;
+    if ((wn >> (m & 63)) & 1ull) {
+      if (l == K) {
+        top[c] = make_uint2(kOctInternal, 0u);
+        return;
+      }
+      p = m;
+      w = wn;
+    } else {
+      top[c] = make_uint2((uint32_t)o.depth[l][slot], __float_as_uint(o.value[l][slot]));
+      return;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_oct_top(const OctreeArgs& oa, int K, uint2* top, hipStream_t s) {
+  const int64_t cells = (int64_t)1 << (3 * K);
+  hipLaunchKernelGGL(k_oct_top, dim3((unsigned)((cells + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, oa, K, top);
+  return hipGetLastError();
+}
+
 }  // namespace sand

@@ -81,7 +81,14 @@ struct OctreeArgs {
   const uint32_t* rank[kMaxOctDepth];
   const uint8_t* depth[kMaxOctDepth + 1];   // level l = 1..D, per child slot
   const float* value[kMaxOctDepth + 1];
+  // Dense index of level top_level (< D), Morton order: per cell the depth
+  // and value bits of the leaf holding it when that leaf is at a level <=
+  // top_level, else x = kOctInternal (descend on from top_level + 1).
+  int top_level;                            // 0: no index
+  int pad2;
+  const uint2* top;
 };
+constexpr uint32_t kOctInternal = 0xffffffffu;
 
 // Bucketed work plan written on the device by the scan kernel.
 struct Plan {
@@ -199,6 +206,8 @@ hipError_t launch_oct_list(const uint64_t* bits, const uint32_t* rank, int64_t w
                            uint64_t* list, hipStream_t s);
 hipError_t launch_oct_samples(const int32_t* near_slots, const uint64_t* parents, int64_t first,
                               int64_t nsamp, int D, int sps, float* xyz, hipStream_t s);
+// Fill the dense top index of an octree (8^K cells of level K).
+hipError_t launch_oct_top(const OctreeArgs& oa, int K, uint2* top, hipStream_t s);
 hipError_t launch_oct_finish(const int32_t* near_slots, int64_t nnear, const uint32_t* depth32,
                              uint8_t* depth, hipStream_t s);
 
