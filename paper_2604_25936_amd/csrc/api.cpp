@@ -425,6 +425,7 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
     for (int i = 0; i < B.L; ++i) {
       a.c0[i] = B.c0[i];
       a.c1[i] = B.c1[i];
+      if (B.kind[i] == 0) a.lin_mask |= 1u << i;
     }
   }
   for (int p = 0; p < 3; ++p) {

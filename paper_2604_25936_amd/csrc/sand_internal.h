@@ -61,6 +61,7 @@ struct ModelArgs {
   size_t chunk_bytes;      // bytes of one hidden chunk
   float c0[kMaxLayers];    // tail bias of the first factor
   float c1[kMaxLayers];    // tail bias of the second factor (1 for linear)
+  uint32_t lin_mask;       // bit j: tail j+1 is linear (second factor a1 = 0, c1 = 1)
 };
 
 // Sparse network-depth octree (Sec. 3.2), pointer-free. Node codes are

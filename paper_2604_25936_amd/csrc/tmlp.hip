@@ -118,21 +118,42 @@ __device__ __forceinline__ void tail_pair_at(int e, float& s0, float& s1, float 
   }
 }
 
+// tail_fma16 for a linear tail: the second factor (a1 = 0) is skipped.
+__device__ __forceinline__ void tail_fma16_lin(float& s0, float w0, const float (&h)[16]) {
+#define SAND_TAIL_L(E, R) \
+  "v_fmac_f32_dpp %0, %1, %" #R " row_newbcast:" #E " row_mask:0xf bank_mask:0xf\n\t"
+  asm("s_nop 1\n\t"
+      SAND_TAIL_L(0, 2) SAND_TAIL_L(1, 3) SAND_TAIL_L(2, 4) SAND_TAIL_L(3, 5)
+      SAND_TAIL_L(4, 6) SAND_TAIL_L(5, 7) SAND_TAIL_L(6, 8) SAND_TAIL_L(7, 9)
+      SAND_TAIL_L(8, 10) SAND_TAIL_L(9, 11) SAND_TAIL_L(10, 12) SAND_TAIL_L(11, 13)
+      SAND_TAIL_L(12, 14) SAND_TAIL_L(13, 15) SAND_TAIL_L(14, 16) SAND_TAIL_L(15, 17)
+      "s_nop 1"
+      : "+v"(s0)
+      : "v"(w0), "v"(h[0]), "v"(h[1]), "v"(h[2]), "v"(h[3]), "v"(h[4]), "v"(h[5]), "v"(h[6]),
+        "v"(h[7]), "v"(h[8]), "v"(h[9]), "v"(h[10]), "v"(h[11]), "v"(h[12]), "v"(h[13]),
+        "v"(h[14]), "v"(h[15]));
+#undef SAND_TAIL_L
+}
+
 // Epilogue of one output block: sine, tail partial sums, pack for the next layer.
 // PACK = false: the layer is the tile's last, so its activations are not
-// converted for a next layer.
-template <int PREC, int KS, bool PACK = true>
+// converted for a next layer. LIN: the tail is linear (s1 stays 0).
+template <int PREC, int KS, bool PACK = true, bool LIN = false>
 __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int rb,
                                          const typename Tr<PREC>::Acc& acc,
                                          typename Tr<PREC>::V (&out)[KS], float& s0, float& s1) {
   using T = Tr<PREC>;
   if constexpr (T::VB == 16) {
     const float w0 = ((const float*)tails)[lane];
-    const float w1 = ((const float*)tails)[64 + lane];
     float h[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) h[e] = sin_rev(acc[e]);
-    tail_fma16(s0, s1, w0, w1, h);
+    if constexpr (LIN) {
+      tail_fma16_lin(s0, w0, h);
+    } else {
+      const float w1 = ((const float*)tails)[64 + lane];
+      tail_fma16(s0, s1, w0, w1, h);
+    }
     if constexpr (PACK) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) T::template put<KS>(out, rb, e, h[e]);
@@ -147,7 +168,7 @@ __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int
         const int e = 4 * i + k;
         const float v = sin_rev(acc[e]);
         s0 = fmaf(ta[k], v, s0);
-        s1 = fmaf(tb[k], v, s1);
+        if constexpr (!LIN) s1 = fmaf(tb[k], v, s1);
         if constexpr (PACK) T::template put<KS>(out, rb, e, v);
       }
     }
@@ -365,8 +386,9 @@ __device__ __forceinline__ float hidden_layer(float y, const char* __restrict__ 
 }
 
 // Layer 1 and the partial sums of its tail, pipelined like the hidden
-// layers: the MFMAs of block rb go with the epilogue of block rb-1.
-template <int PREC, int WP, bool PACK>
+// layers: the MFMAs of block rb go with the epilogue of block rb-1. LIN: tail
+// 1 is linear.
+template <int PREC, int WP, bool PACK, bool LIN>
 __device__ __forceinline__ void layer1(const char* l1, int lane, int g, float px, float py,
                                        float pz, typename Tr<PREC>::V (&act)[Cfg<PREC, WP>::KS],
                                        float& s0, float& s1) {
@@ -383,8 +405,8 @@ __device__ __forceinline__ void layer1(const char* l1, int lane, int g, float px
         acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
     }
     if (rb > 0) {
-      epilogue<PREC, C::KS, PACK>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1, prev,
-                                  act, s0, s1);
+      epilogue<PREC, C::KS, PACK, LIN>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1,
+                                       prev, act, s0, s1);
       pin_block<PREC, C::KS, PACK>(act, rb - 1, s0, s1);
     }
     prev = acc;
@@ -487,10 +509,18 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
 
   V actA[C::KS], actB[C::KS];
   float s0 = 0.0f, s1 = 0.0f;
-  if (d > 1)
-    layer1<PREC, WP, true>(l1, lane, g, px, py, pz, actA, s0, s1);
-  else
-    layer1<PREC, WP, false>(l1, lane, g, px, py, pz, actA, s0, s1);
+  const bool lin1 = (M.lin_mask & 1u) != 0;
+  if (d > 1) {
+    if (lin1)
+      layer1<PREC, WP, true, true>(l1, lane, g, px, py, pz, actA, s0, s1);
+    else
+      layer1<PREC, WP, true, false>(l1, lane, g, px, py, pz, actA, s0, s1);
+  } else {
+    if (lin1)
+      layer1<PREC, WP, false, true>(l1, lane, g, px, py, pz, actA, s0, s1);
+    else
+      layer1<PREC, WP, false, false>(l1, lane, g, px, py, pz, actA, s0, s1);
+  }
   float y = add_tail<PREC>(0.0f, s0, s1, M.c0[0], M.c1[0]);
   // every accumulated output y_j, for building a depth map (Eq. 5)
   float* yrow = (y_all && g == 0 && ok) ? y_all + (int64_t)gi * M.L : nullptr;
