@@ -404,6 +404,9 @@ __device__ __forceinline__ void layer1(const char* l1, int lane, int g, float px
       for (int st = 0; st < T::L1S; ++st)
         acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
     }
+    // both MFMAs of block rb go out before block rb-1's epilogue reads its
+    // own (older) results, so no read waits on an MFMA still in flight
+    __builtin_amdgcn_sched_barrier(0);
     if (rb > 0) {
       epilogue<PREC, C::KS, PACK, LIN>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1,
                                        prev, act, s0, s1);
