@@ -87,6 +87,7 @@ def test_null_arguments():
     o = sand.QueryOpts()
     lib.sand_query_opts_init(ctypes.byref(o))
     assert o.precision == 0 and o.mode == 0 and o.max_depth == 0
+    assert o.dynamic_r == 0.0 and o.dynamic_checkpoint == 0
     assert lib.sand_query(None, None, None, 0, None, ctypes.byref(o), None) == sand.ERR_INVALID
     assert lib.sand_model_info(None, None, None) == sand.ERR_INVALID
     info = sand.MapInfo()

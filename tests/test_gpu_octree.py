@@ -164,3 +164,20 @@ def test_closed_form_trees_and_server():
         sand.construct_octree(model, D=11)
     with pytest.raises(sand.SandError):
         sand.construct_octree(model, D=4, s=3)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_shallow_trees(D):
+    """Trees with no dense top index (D = 1) or a one- or two-level one."""
+    s, r = 2, 0.3
+    say(f"case: 3x10 plain-init model, octree D={D}, s={s}, r={r}, fp32")
+    blob = synth.write_blob(synth.siren_tmlp(67, 3, 10, tails="mult", scale="plain"))
+    ref = oracle.parse_blob(blob)
+    model = sand.load_model(blob, 0)
+    dm, info = sand.construct_octree(model, D=D, s=s, r=r)
+    tree = OT.build(ref, D, s, r)
+    assert [len(tree["internal"][l]) for l in range(D)] == info["internal_nodes"][:D]
+    x = np.random.Generator(np.random.PCG64(30 + D)).uniform(-1.05, 1.05, size=(9000, 3))
+    x = x.astype(np.float32)
+    y, d = gpu_query(model, dm, x)
+    compare(ref, tree, x.astype(np.float64), y, d, s, r, "fp32", 1e-5, f"D={D}")
