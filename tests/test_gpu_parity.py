@@ -270,3 +270,33 @@ def test_free_model_before_map():
     t = torch.full((1000,), 7, dtype=torch.uint8, device=DEV)
     torch.cuda.synchronize()
     assert int(t.sum().item()) == 7000
+
+
+@pytest.mark.parametrize("kind", ["dense", "octree"])
+def test_unaligned_buffers(kind):
+    """Points, results and depths at odd offsets (the 4-points-per-thread
+    lookup and scatter then take their element-wise paths) give the same bits
+    as aligned buffers; sizes not a multiple of 4."""
+    blob = c2_blob(256)
+    model = sand.load_model(blob, 0)
+    if kind == "dense":
+        dm = sand.build_depthmap(model, c2_map())
+    else:
+        dm, _ = sand.construct_octree(model, D=6, s=1, r=1.5e-4)
+    pts = c2_points(20001, seed=41)
+    n = len(pts)
+    say(f"case: unaligned buffers, {kind} map, n={n}")
+    base = torch.from_numpy(np.ascontiguousarray(pts)).to(DEV)
+    y_ref = torch.empty(n, device=DEV)
+    d_ref = torch.empty(n, dtype=torch.uint8, device=DEV)
+    sand.query(model, dm, base, out=y_ref, precision="bf16", depth_out=d_ref)
+    xbuf = torch.empty((n + 1, 3), device=DEV)
+    xbuf[1:] = base
+    ybuf = torch.empty(n + 1, device=DEV)
+    dbuf = torch.empty(n + 3, dtype=torch.uint8, device=DEV)
+    xs, ys, ds = xbuf[1:], ybuf[1:], dbuf[3:]
+    assert xs.data_ptr() % 16 != 0 and ys.data_ptr() % 16 != 0 and ds.data_ptr() % 4 != 0
+    sand.query(model, dm, xs, out=ys, precision="bf16", depth_out=ds)
+    torch.cuda.synchronize()
+    assert torch.equal(ds, d_ref)
+    assert torch.equal(ys.view(torch.int32), y_ref.view(torch.int32))
