@@ -38,10 +38,16 @@ def log(msg):
 
 
 def kernel_hash():
+    """Hash of the T-MLP kernel's code (comments and blank lines removed, so
+    that only a change of code invalidates the committed traffic counters)."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            t = f.read()
+        t = re.sub(r"/\*.*?\*/", "", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", "", t)
+        h.update("\n".join(ln.rstrip() for ln in t.split("\n") if ln.strip()).encode())
     return h.hexdigest()[:16]
 
 

@@ -15,17 +15,20 @@
 //    accumulators, after sine and conversion, are the next layer's B
 //    operand as they stand: activations never leave registers.
 //  * Layer 1 (K = 3 plus bias) is an FP32 MFMA with B = (x, y, z, 1): its
-//    omega-scaled argument is FP32 in every precision.
+//    omega-scaled argument is FP32 in every precision. A linear first tail
+//    skips its zero second factor.
 //  * Hidden-layer bias: one extra K step against a constant B = 1 (two
 //    16-bit columns, high and low part, for BF16/FP16).
 //  * Epilogue per element: hardware sine in revolutions (weights carry
 //    omega/(2 pi)), two FP32 FMAs for the two tail factors, pack. The lanes
 //    holding disjoint units of one point are summed by cross-lane exchange.
-//  * Weights stream through a three-slot LDS ring, one output block
-//    ("chunk") at a time: direct global-to-LDS loads of chunk c+1 are in
-//    flight while chunk c feeds the MFMAs.
+//  * Weights stream through an LDS ring of PD + 2 slots, one output block
+//    ("chunk") at a time: direct global-to-LDS loads of the next PD chunks
+//    are in flight while chunk c feeds the MFMAs (PD = 1 by default).
 //  * Software pipelining: each wavefront issues the MFMAs of block rb
-//    together with the sine/tail epilogue of block rb-1.
+//    together with the sine/tail epilogue of block rb-1; for BF16/FP16 the
+//    block step is scheduled by hand, each MFMA carrying a share of that
+//    epilogue and the A operands arriving in batches one batch ahead.
 //  * Two wavefronts per SIMD: while one wavefront runs its sine/tail
 //    epilogue on the vector ALU the other keeps the matrix core busy. By
 //    default one workgroup of eight wavefronts per CU shares each weight
@@ -33,7 +36,10 @@
 //    workgroups of four per CU instead (each with its own ring), which
 //    measured slower on the 8x256 model (twice the weight traffic).
 // The grid is persistent and strides over tiles, which the plan orders
-// deepest bucket first.
+// deepest bucket first; each tile's points and the first hidden chunk are
+// fetched while the previous tile runs. Map-free dynamic exit runs in the
+// same kernel (per-layer exit test, optional compaction of the points still
+// running after a checkpoint layer into full tiles of a second launch).
 
 #include <type_traits>
 
