@@ -370,9 +370,13 @@ def serving_leg(sand, torch, inputs, n_models, n_payloads=128, n_measure=2000):
         order = [int(i) for i in rng.integers(0, n_payloads, size=n_measure)]
         log(f"serving: Poisson {rate:.0f} requests/s ({load}x saturation), {n_measure} requests")
         lat, pts, span, st = run(order, gaps)
+        dev = [s["t_done"] - s["t_submit"] for s in st]       # results complete on the device
+        d2h = [s["t_copied"] - s["t_done"] for s in st]       # the copy back to the host
         out["loads"][str(load)] = {
             "offered_requests_per_s": rate, "queries_per_s": pts / span,
             "p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+            "device_p50_ms": percentile(dev, 50) * 1e3, "device_p99_ms": percentile(dev, 99) * 1e3,
+            "d2h_p50_ms": percentile(d2h, 50) * 1e3, "d2h_p99_ms": percentile(d2h, 99) * 1e3,
             "mean_batch_requests": float(np.mean([s["batch_size"] for s in st])),
         }
     info = srv.stats()
