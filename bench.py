@@ -397,11 +397,18 @@ def grad_leg(sand, torch, inputs, dm_model):
     sdf = torch.empty(n, dtype=torch.float32, device="cuda:0")
     g = torch.empty((n, 3), dtype=torch.float32, device="cuda:0")
     out = {"points": n}
+    depth = torch.empty(n, dtype=torch.uint8, device="cuda:0")
     for prec in ("bf16", "fp32"):
         ws = torch.empty(sand.query_grad_workspace_size(model, n, prec), dtype=torch.uint8,
                          device="cuda:0")
         t = time_steps(lambda: sand.query_grad(model, dm, xyz, sdf_out=sdf, grad_out=g,
                                                precision=prec, workspace=ws), 5, 2)
+        sand.query_grad(model, dm, xyz, sdf_out=sdf, grad_out=g, precision=prec, workspace=ws,
+                        depth_out=depth)
+        hist = torch.bincount(depth.to(torch.int64), minlength=L + 1).cpu().numpy()
+        # algorithmic MFMA work: the forward and the transposed backward products,
+        # 2 (d - 1) W^2 flop each per point (whole step, bucketing included)
+        fl = 2 * hidden_flops(hist, W)
         idx = np.random.Generator(np.random.PCG64(3)).choice(n, 4000, replace=False)
         ref = oracle.parse_blob(blob)
         d = oracle.lookup_depth(x[idx], dmap, L)
@@ -409,6 +416,8 @@ def grad_leg(sand, torch, inputs, dm_model):
         got = g.cpu().numpy()[idx].astype(np.float64)
         rel = np.linalg.norm(got - want, axis=1) / np.maximum(np.linalg.norm(want, axis=1), 1e-12)
         out[prec] = {"queries_per_s": n / t, "ms_per_step": t * 1e3,
+                     "mean_exit_depth": float((hist * np.arange(L + 1)).sum() / max(1, hist.sum())),
+                     "mfma_tflops_step": fl / t / 1e12, "mfma_frac_step": fl / t / 1e12 / PEAK[prec],
                      "grad_max_rel_err_4k_sample": float(rel.max()),
                      "grad_mean_rel_err_4k_sample": float(rel.mean())}
     return out
