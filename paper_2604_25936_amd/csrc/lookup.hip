@@ -152,17 +152,36 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Add the wavefront's points to hist[depth]: one LDS atomic per distinct
-// depth present in the wavefront.
-__device__ __forceinline__ void wave_histogram(int d, bool valid, int* hist) {
-  uint64_t todo = __ballot(valid);
+// Add the wavefront's points (P per lane) to hist[depth]: one LDS atomic per
+// distinct depth present in the wavefront, whatever slot it occurs in.
+template <int P>
+__device__ __forceinline__ void wave_histogram_n(const int (&d)[P], const bool (&valid)[P],
+                                                 int* hist) {
   const int lane = threadIdx.x & 63;
-  while (todo) {
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const int v = __shfl(d, leader);
-    const uint64_t m = __ballot(valid && d == v);
-    if (lane == leader) atomicAdd(&hist[v], __popcll(m));
-    todo &= ~m;
+  bool todo[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) todo[j] = valid[j];
+  for (;;) {
+    bool mine_any = false;
+    int mine = 0;
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j)
+      if (todo[j]) {
+        mine_any = true;
+        mine = d[j];
+      }
+    const uint64_t any = __ballot(mine_any);
+    if (!any) break;
+    const int leader = __ffsll((unsigned long long)any) - 1;
+    const int v = __shfl(mine, leader);
+    int total = 0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const bool hit = valid[j] && d[j] == v;
+      total += __popcll(__ballot(hit));
+      if (hit) todo[j] = false;
+    }
+    if (lane == leader) atomicAdd(&hist[v], total);
   }
 }
 
@@ -271,13 +290,14 @@ __device__ __forceinline__ void lookup_block(
           if (q0 + i < n && d[i] == 0) sdf[q0 + i] = farv[i];
       }
     }
+    bool valid[kPP];
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {
       const int64_t q = q0 + i;
-      const bool valid = q < n;
-      if (valid && d[i] == 0 && grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
-      wave_histogram(d[i], valid, hist);
+      valid[i] = q < n;
+      if (valid[i] && d[i] == 0 && grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
     }
+    wave_histogram_n<kPP>(d, valid, hist);
   }
   __syncthreads();
   if (t < kBuckets) counts[blk * kBuckets + t] = hist[t];
