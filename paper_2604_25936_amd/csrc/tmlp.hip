@@ -144,6 +144,27 @@ __device__ __forceinline__ void tail_fma16_lin(float& s0, float w0, const float 
 // Epilogue of one output block: sine, tail partial sums, pack for the next layer.
 // PACK = false: the layer is the tile's last, so its activations are not
 // converted for a next layer. LIN: the tail is linear (s1 stays 0).
+// BF16/FP16 form with the block's lane-indexed tail weights w0, w1 already
+// in registers.
+template <int PREC, int KS, bool PACK, bool LIN>
+__device__ __forceinline__ void epilogue16(float w0, float w1, int rb,
+                                           const typename Tr<PREC>::Acc& acc,
+                                           typename Tr<PREC>::V (&out)[KS], float& s0,
+                                           float& s1) {
+  using T = Tr<PREC>;
+  float h[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) h[e] = sin_rev(acc[e]);
+  if constexpr (LIN)
+    tail_fma16_lin(s0, w0, h);
+  else
+    tail_fma16(s0, s1, w0, w1, h);
+  if constexpr (PACK) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) T::template put<KS>(out, rb, e, h[e]);
+  }
+}
+
 template <int PREC, int KS, bool PACK = true, bool LIN = false>
 __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int rb,
                                          const typename Tr<PREC>::Acc& acc,
@@ -151,19 +172,8 @@ __device__ __forceinline__ void epilogue(const char* tails, int lane, int g, int
   using T = Tr<PREC>;
   if constexpr (T::VB == 16) {
     const float w0 = ((const float*)tails)[lane];
-    float h[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) h[e] = sin_rev(acc[e]);
-    if constexpr (LIN) {
-      tail_fma16_lin(s0, w0, h);
-    } else {
-      const float w1 = ((const float*)tails)[64 + lane];
-      tail_fma16(s0, s1, w0, w1, h);
-    }
-    if constexpr (PACK) {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) T::template put<KS>(out, rb, e, h[e]);
-    }
+    const float w1 = LIN ? 0.0f : ((const float*)tails)[64 + lane];
+    epilogue16<PREC, KS, PACK, LIN>(w0, w1, rb, acc, out, s0, s1);
   } else {
 #pragma unroll
     for (int i = 0; i < T::NR / 4; ++i) {
@@ -400,22 +410,39 @@ __device__ __forceinline__ void layer1(const char* l1, int lane, int g, float px
                                        float& s0, float& s1) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
+  // The layer's LDS operands (the A operands and, for BF16/FP16, the
+  // lane-indexed tail weights) are read up front, so the layer waits for
+  // LDS once instead of twice per block.
+  float a[C::RB][T::L1S];
+  float w0[C::RB], w1[C::RB];
+#pragma unroll
+  for (int rb = 0; rb < C::RB; ++rb) {
+    const float* ch = (const float*)(l1 + rb * C::L1C);
+#pragma unroll
+    for (int st = 0; st < T::L1S; ++st) a[rb][st] = ch[st * 64 + lane];
+    if constexpr (T::VB == 16) {
+      w0[rb] = ch[T::L1S * 64 + lane];
+      w1[rb] = LIN ? 0.0f : ch[T::L1S * 64 + 64 + lane];
+    }
+  }
   typename T::Acc prev = {};
 #pragma unroll
   for (int rb = 0; rb <= C::RB; ++rb) {
     typename T::Acc acc = {};
     if (rb < C::RB) {
-      const char* ch = l1 + rb * C::L1C;
 #pragma unroll
       for (int st = 0; st < T::L1S; ++st)
-        acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
+        acc = T::mma1(a[rb][st], T::l1_b(st, g, px, py, pz), acc);
     }
     // both MFMAs of block rb go out before block rb-1's epilogue reads its
     // own (older) results, so no read waits on an MFMA still in flight
     __builtin_amdgcn_sched_barrier(0);
     if (rb > 0) {
-      epilogue<PREC, C::KS, PACK, LIN>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1,
-                                       prev, act, s0, s1);
+      if constexpr (T::VB == 16)
+        epilogue16<PREC, C::KS, PACK, LIN>(w0[rb - 1], w1[rb - 1], rb - 1, prev, act, s0, s1);
+      else
+        epilogue<PREC, C::KS, PACK, LIN>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1,
+                                         prev, act, s0, s1);
       pin_block<PREC, C::KS, PACK>(act, rb - 1, s0, s1);
     }
     prev = acc;
@@ -495,8 +522,11 @@ __device__ __forceinline__ void spill_points(const DynSpill& sp, bool running, i
 
 // Evaluate one tile of exit depth d. This lane's point is gi (< 0: none)
 // at (px, py, pz); every lane of the same column holds the same point.
+// Returns whether this lane writes the point's result, yout, to the output
+// (left to the caller, which can first settle its own loads: a wait placed
+// after a conditional store must assume the store is still outstanding).
 template <int PREC, int WP>
-__device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__ sdf, int d,
+__device__ __forceinline__ bool run_tile(const ModelArgs& M, float& yout, int d,
                                          int gi, float px, float py, float pz, char* ring,
                                          const char* l1, int lane, int wave,
                                          float* __restrict__ y_all, float dyn_r,
@@ -582,7 +612,8 @@ __device__ __forceinline__ void run_tile(const ModelArgs& M, float* __restrict__
     wait_chunk();
     __syncthreads();
   }
-  if (g == 0 && done) sdf[gi] = y;
+  yout = y;
+  return g == 0 && done;
 }
 
 // A resumed tile of compacted dynamic exit: up to Q records, each run from
@@ -658,18 +689,39 @@ __device__ __forceinline__ void load_layer1(const ModelArgs& M, char* l1, int ti
   for (int i = tid; i < C::L1B / 16; i += C::NTF) ((uint4*)l1)[i] = ((const uint4*)M.chunks)[i];
 }
 
+// A workgroup's walk over its tiles, in increasing order. The plan puts
+// deeper buckets first, so along the walk the exit depth only falls and a
+// bucket's bounds are read (from the workgroup's LDS copy of the plan) only
+// when the walk enters it. Bucket d holds tiles [lo, hi).
+struct TileWalk {
+  int d;
+  int64_t lo, hi, start, count;
+};
+
 // Exit depth of tile `tile` and this lane's point in it (-1: none; qi is
-// the lane's slot in the tile). The plan is the workgroup's LDS copy.
+// the lane's slot in the tile). Successive calls ask for increasing tiles.
 template <int Q>
-__device__ __forceinline__ int tile_point(const QueryArgs& a, const Plan& plan, int64_t total,
-                                          int64_t tile, int qi, int& d) {
+__device__ __forceinline__ int tile_point(const QueryArgs& a, const Plan& plan, TileWalk& w,
+                                          int64_t total, int64_t tile, int qi, int& d) {
   int64_t start, cnt;
   if (tile >= total) {
     d = 1;
     return -1;
   }
   if (a.plan) {
-    decode_tile<Q>(&plan, a.m.L, tile, d, start, cnt);
+    // ends by bucket 1 at the latest: tile < total = tile_end[1]
+    while (tile >= w.hi && w.d > 1) {
+      --w.d;
+      w.lo = w.hi;
+      w.hi = plan.tile_end[w.d];
+      w.start = plan.start[w.d];
+      w.count = plan.count[w.d];
+    }
+    d = w.d;
+    const int64_t local = tile - w.lo;
+    start = w.start + local * Q;
+    cnt = w.count - local * Q;
+    if (cnt > Q) cnt = Q;
   } else {
     d = a.full_depth;
     start = tile * Q;
@@ -715,9 +767,11 @@ void k_tmlp(QueryArgs a) {
   const int64_t G = gridDim.x;
   const int qi = wave * T::NQ + T::col(lane);
   int64_t tile = blockIdx.x;
+  // buckets above L are empty: the walk starts past the deepest one
+  TileWalk walk{a.m.L + 1, 0, 0, 0, 0};
   int d, d_next;
-  int gi = tile_point<Q>(a, plan, total, tile, qi, d);
-  int gi_next = tile_point<Q>(a, plan, total, tile + G, qi, d_next);
+  int gi = tile_point<Q>(a, plan, walk, total, tile, qi, d);
+  int gi_next = tile_point<Q>(a, plan, walk, total, tile + G, qi, d_next);
   float px, py, pz;
   point_coords(a.xyz, gi, px, py, pz);
   // Consume the first loads here: otherwise the loop entry merges their
@@ -726,11 +780,17 @@ void k_tmlp(QueryArgs a) {
   asm volatile("" ::"v"(gi_next), "v"(px), "v"(py), "v"(pz));
   for (; tile < total; tile += G) {
     int d_after;
-    const int gi_after = tile_point<Q>(a, plan, total, tile + 2 * G, qi, d_after);
+    const int gi_after = tile_point<Q>(a, plan, walk, total, tile + 2 * G, qi, d_after);
     float nx, ny, nz;
     point_coords(a.xyz, gi_next, nx, ny, nz);
-    run_tile<PREC, WP>(a.m, a.sdf, d, gi, px, py, pz, ring, l1, lane, wave, a.y_all, a.dyn_r,
-                       a.depth_out, a.spill);
+    float y;
+    const bool st = run_tile<PREC, WP>(a.m, y, d, gi, px, py, pz, ring, l1, lane, wave, a.y_all,
+                                       a.dyn_r, a.depth_out, a.spill);
+    // The next tiles' prefetched coordinates and permutation entries have
+    // had a whole tile to land: take them before the store, so that moving
+    // them into place at the loop's end needs no wait for the store.
+    asm volatile("" ::"v"(gi_after), "v"(nx), "v"(ny), "v"(nz));
+    if (st) a.sdf[gi] = y;
     d = d_next;
     gi = gi_next;
     px = nx;
@@ -776,8 +836,10 @@ void k_tmlp_batch(BatchArgs a) {
     const int gi = qi < cnt ? q.perm[start + qi] : -1;
     float px, py, pz;
     point_coords(q.xyz, gi, px, py, pz);
-    run_tile<PREC, WP>(M, q.sdf, d, gi, px, py, pz, ring, l1, lane, wave, nullptr, 0.0f,
-                       nullptr, DynSpill{});
+    float y;
+    if (run_tile<PREC, WP>(M, y, d, gi, px, py, pz, ring, l1, lane, wave, nullptr, 0.0f, nullptr,
+                           DynSpill{}))
+      q.sdf[gi] = y;
   }
 }
 
