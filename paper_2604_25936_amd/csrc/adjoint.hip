@@ -308,8 +308,8 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       typename T::Acc acc = {};
 #pragma unroll
       for (int st = 0; st < T::L1S; ++st)
-        acc = T::mma1(((const float*)ch)[st * 64 + lane], T::l1_b(st, g, px, py, pz), acc);
-      fwd_epilogue<PREC, C::KS>(ch + T::L1S * 256, g, rb, acc, actA, s0, s1,
+        acc = T::mma1(T::l1_a(ch, st, lane), T::l1_b(st, g, px, py, pz), acc);
+      fwd_epilogue<PREC, C::KS>(ch + T::L1S * T::L1AB, g, rb, acc, actA, s0, s1,
                                 stash_at<PREC, WP>(stash, 1, rb));
     }
     float u0 = T::lane_sum(s0) + q.m.c0[0], u1 = T::lane_sum(s1) + q.m.c1[0];

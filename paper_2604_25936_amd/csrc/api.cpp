@@ -206,7 +206,7 @@ struct Geo {
     RB = WP / BM;
     KS = WP / KPS;
     CH = (KS + 1) * 64 * VB + TAILB;
-    L1C = L1S * 256 + TAILB;
+    L1C = L1S * (prec == PREC_FP32 ? 256 : 64 * 16) + TAILB;
   }
 };
 
@@ -236,25 +236,51 @@ std::vector<char> pack(const Blob& B, int prec, int WP) {
     }
   };
   // layer 1
+  // v = h + m + l, each part a BF16 (the kernels' 16-bit paths evaluate
+  // layer 1 on BF16 MFMAs over three-way splits of weights and coordinates)
+  auto split3 = [](double v, uint16_t (&p)[3]) {
+    for (int i = 0; i < 3; ++i) {
+      p[i] = to_bf16((float)v);
+      v -= (double)from_16(p[i], PREC_BF16);
+    }
+  };
   for (int rb = 0; rb < G.RB; ++rb) {
     char* ch = buf.data() + (size_t)rb * G.L1C;
-    float* A = (float*)ch;
     for (int st = 0; st < G.L1S; ++st)
       for (int l = 0; l < 64; ++l) {
-        int m, k;
         if (prec == PREC_FP32) {
-          m = l & 15;
-          k = l >> 4;
+          // K = (x, y, z, 1) across the four 16-lane groups
+          const int m = l & 15, k = l >> 4, u = G.BM * rb + m;
+          double v = 0.0;
+          if (u < W) v = s1 * (k < 3 ? (double)B.Wm[0][u * 3 + k] : (double)B.b[0][u]);
+          ((float*)ch)[st * 64 + l] = (float)v;
         } else {
-          m = l & 31;
-          k = 2 * st + (l >> 5);
+          // lane half hh of step st holds coordinate c = 2 st + hh: the
+          // weight parts of the products (wh, wh, wm, wh, wm, wl) whose
+          // coordinate parts are (ch, cm, ch, cl, cm, ch), then bias parts
+          // against constant 1s: bh, bm (step 0, half 0), bl (step 0, half 1)
+          const int m = l & 31, hh = l >> 5, u = G.BM * rb + m, c = 2 * st + hh;
+          uint16_t* A = (uint16_t*)(ch + ((size_t)st * 64 + l) * 16);
+          for (int p = 0; p < 8; ++p) A[p] = 0;
+          if (u >= W) continue;
+          uint16_t w[3];
+          if (c < 3) {
+            split3(s1 * (double)B.Wm[0][u * 3 + c], w);
+            const int part[6] = {0, 0, 1, 0, 1, 2};
+            for (int i = 0; i < 6; ++i) A[i] = w[part[i]];
+          }
+          if (st == 0) {
+            split3(s1 * (double)B.b[0][u], w);
+            if (hh == 0) {
+              A[6] = w[0];
+              A[7] = w[1];
+            } else {
+              A[6] = w[2];
+            }
+          }
         }
-        const int u = G.BM * rb + m;
-        double v = 0.0;
-        if (u < W) v = s1 * (k < 3 ? (double)B.Wm[0][u * 3 + k] : (double)B.b[0][u]);
-        A[st * 64 + l] = (float)v;
       }
-    tails((float*)(ch + G.L1S * 256), 0, rb);
+    tails((float*)(ch + (size_t)G.L1C - G.TAILB), 0, rb);
   }
   // hidden layers
   for (int j = 1; j < B.L; ++j) {

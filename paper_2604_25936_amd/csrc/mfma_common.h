@@ -35,12 +35,18 @@ struct Tr<PREC_FP32> {
   static constexpr int SPB = 4;   // K steps per block of input units
   static constexpr int VB = 4;    // A-operand bytes per lane per K step
   static constexpr int L1S = 1;   // layer-1 MFMA steps
+  // layer 1: FP32 MFMA, K = (x, y, z, 1); A-operand bytes per step
+  using L1V = float;
+  static constexpr int L1AB = 256;
   __device__ __forceinline__ static int col(int lane) { return lane & 15; }
   __device__ __forceinline__ static int grp(int lane) { return lane >> 4; }
   __device__ __forceinline__ static Acc mma(V a, V b, Acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) { return mma(a, b, c); }
+  __device__ __forceinline__ static float l1_a(const char* ch, int step, int lane) {
+    return ((const float*)ch)[step * 64 + lane];
+  }
   __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
     return g == 0 ? x : g == 1 ? y : g == 2 ? z : 1.0f;
   }
@@ -68,9 +74,44 @@ struct Tr<PREC_FP32> {
   }
 };
 
+// v = h + m + l exactly, each part a BF16 (round to nearest even): the
+// residuals v - h and v - h - m are exact in FP32, and after two 8-bit parts
+// at most 8 significant bits remain.
+__device__ __forceinline__ void split3_bf16(float v, __bf16& h, __bf16& m, __bf16& l) {
+  h = (__bf16)v;
+  const float r = v - (float)h;
+  m = (__bf16)r;
+  l = (__bf16)(r - (float)m);
+}
+
 template <int PREC>
 struct Tr16 {
   using Acc = f32x16;
+  // Layer 1 of the 16-bit paths runs on BF16 MFMAs with the weights (host)
+  // and the coordinates split three ways, w = wh + wm + wl and c = ch + cm +
+  // cl: the six partial products of order 2^-16 and above (wh ch, wh cm,
+  // wm ch, wh cl, wm cm, wl ch), exact in BF16 x BF16 and summed in FP32,
+  // give the omega-scaled argument to about 2^-24 relative, as an FP32
+  // product would. K slots (step, lane half): (0, 0) the six products of x
+  // and the bias parts bh, bm; (0, 1) those of y and bl; (1, 0) those of z;
+  // (1, 1) zero. An FP32 MFMA would hold the vector ALU for its whole
+  // duration; the BF16 ones run beside the sines.
+  using L1V = bf16x8;
+  static constexpr int L1AB = 64 * 16;
+  __device__ __forceinline__ static Acc mma1(bf16x8 a, bf16x8 b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static bf16x8 l1_a(const char* ch, int step, int lane) {
+    return *(const bf16x8*)(ch + (step * 64 + lane) * 16);
+  }
+  __device__ __forceinline__ static bf16x8 l1_b(int step, int g, float x, float y, float z) {
+    const float c = step == 0 ? (g == 0 ? x : y) : (g == 0 ? z : 0.0f);
+    __bf16 h, m, l;
+    split3_bf16(c, h, m, l);
+    const __bf16 one = (__bf16)(step == 0 ? 1.0f : 0.0f);
+    const __bf16 one0 = (__bf16)(step == 0 && g == 0 ? 1.0f : 0.0f);
+    return bf16x8{h, m, h, l, m, h, one, one0};
+  }
   // store a block's NR values (in register order) as next-layer B operands,
   // each 8-wide vector built fresh so no earlier contents stay live
   template <class V, class E, int KS>
@@ -91,12 +132,6 @@ struct Tr16 {
   static constexpr int L1S = 2;
   __device__ __forceinline__ static int col(int lane) { return lane & 31; }
   __device__ __forceinline__ static int grp(int lane) { return lane >> 5; }
-  __device__ __forceinline__ static Acc mma1(float a, float b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-  }
-  __device__ __forceinline__ static float l1_b(int step, int g, float x, float y, float z) {
-    return step == 0 ? (g == 0 ? x : y) : (g == 0 ? z : 1.0f);
-  }
   __device__ __forceinline__ static int tail_row(int i, int g) { return 8 * i + 4 * g; }
   // forward-chunk tail weights, lane-indexed: for factor f, lane l holds the
   // weight of the unit in its own register e = l & 15 (row group g = l >> 5),
@@ -179,7 +214,7 @@ struct Cfg {
   // adjoint chunk (transposed weights, no bias), then tail weights
   static constexpr int TAIL_OFF_B = KS * 64 * T::VB;
   static constexpr int CH_B = TAIL_OFF_B + T::BM * 8;
-  static constexpr int L1C = T::L1S * 256 + T::TAILB;    // layer-1 chunk bytes
+  static constexpr int L1C = T::L1S * T::L1AB + T::TAILB;    // layer-1 chunk bytes
   static constexpr int L1B = RB * L1C;
   static constexpr int PD = SAND_PD;                     // forward chunks in flight
   static constexpr int NSLOT = PD + 2;                   // forward LDS ring slots

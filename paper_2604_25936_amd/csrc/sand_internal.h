@@ -14,8 +14,10 @@
 //
 //     layer 1, FP32 path (16x16x4 FP32 MFMA, K = 4 = x, y, z, bias):
 //        float A[1 step][64 lanes], then tails             256 + 128 B
-//     layer 1, BF16/FP16 path (32x32x2 FP32 MFMA, 2 K steps):
-//        float A[2 steps][64 lanes], then tails            512 + 512 B
+//     layer 1, BF16/FP16 path (32x32x16 BF16 MFMA, 2 K steps, on three-way
+//     BF16 splits of the weights and coordinates: lane half h of step s
+//     holds the six products of coordinate 2s + h and bias parts):
+//        u16 A[2 steps][64 lanes][8], then tails          2048 + 512 B
 //     layer j >= 2, FP32 (16x16x4 MFMA, WP/4 K steps + 1 bias step):
 //        float A[WP/4 + 1][64 lanes], then tails
 //     layer j >= 2, BF16/FP16 (32x32x16 MFMA, WP/16 K steps + 1 bias step):

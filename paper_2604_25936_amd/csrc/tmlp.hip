@@ -410,29 +410,37 @@ __device__ __forceinline__ void layer1(const char* l1, int lane, int g, float px
                                        float& s0, float& s1) {
   using C = Cfg<PREC, WP>;
   using T = Tr<PREC>;
-  // The layer's LDS operands (the A operands and, for BF16/FP16, the
-  // lane-indexed tail weights) are read up front, so the layer waits for
-  // LDS once instead of twice per block.
-  float a[C::RB][T::L1S];
+  // The lane-indexed tail weights (BF16/FP16) are read up front and the A
+  // operands one block ahead, so no LDS read is awaited right after its
+  // issue.
+  using L1V = typename T::L1V;
   float w0[C::RB], w1[C::RB];
+  if constexpr (T::VB == 16) {
 #pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb) {
-    const float* ch = (const float*)(l1 + rb * C::L1C);
-#pragma unroll
-    for (int st = 0; st < T::L1S; ++st) a[rb][st] = ch[st * 64 + lane];
-    if constexpr (T::VB == 16) {
-      w0[rb] = ch[T::L1S * 64 + lane];
-      w1[rb] = LIN ? 0.0f : ch[T::L1S * 64 + 64 + lane];
+    for (int rb = 0; rb < C::RB; ++rb) {
+      const float* tails = (const float*)(l1 + rb * C::L1C + T::L1S * T::L1AB);
+      w0[rb] = tails[lane];
+      w1[rb] = LIN ? 0.0f : tails[64 + lane];
     }
+  }
+  L1V a[2][T::L1S], b[T::L1S];
+#pragma unroll
+  for (int st = 0; st < T::L1S; ++st) {
+    a[0][st] = T::l1_a(l1, st, lane);
+    b[st] = T::l1_b(st, g, px, py, pz);
   }
   typename T::Acc prev = {};
 #pragma unroll
   for (int rb = 0; rb <= C::RB; ++rb) {
     typename T::Acc acc = {};
     if (rb < C::RB) {
+      if (rb + 1 < C::RB) {
 #pragma unroll
-      for (int st = 0; st < T::L1S; ++st)
-        acc = T::mma1(a[rb][st], T::l1_b(st, g, px, py, pz), acc);
+        for (int st = 0; st < T::L1S; ++st)
+          a[(rb + 1) & 1][st] = T::l1_a(l1 + (rb + 1) * C::L1C, st, lane);
+      }
+#pragma unroll
+      for (int st = 0; st < T::L1S; ++st) acc = T::mma1(a[rb & 1][st], b[st], acc);
     }
     // both MFMAs of block rb go out before block rb-1's epilogue reads its
     // own (older) results, so no read waits on an MFMA still in flight
@@ -441,7 +449,7 @@ __device__ __forceinline__ void layer1(const char* l1, int lane, int g, float px
       if constexpr (T::VB == 16)
         epilogue16<PREC, C::KS, PACK, LIN>(w0[rb - 1], w1[rb - 1], rb - 1, prev, act, s0, s1);
       else
-        epilogue<PREC, C::KS, PACK, LIN>(l1 + (rb - 1) * C::L1C + T::L1S * 256, lane, g, rb - 1,
+        epilogue<PREC, C::KS, PACK, LIN>(l1 + (rb - 1) * C::L1C + T::L1S * T::L1AB, lane, g, rb - 1,
                                          prev, act, s0, s1);
       pin_block<PREC, C::KS, PACK>(act, rb - 1, s0, s1);
     }

@@ -180,6 +180,30 @@ def test_c2_model_medium(prec):
     assert_close(y, oracle.forward(ref, xs, np.full(len(xs), 8)), TOL[prec], f"8x256 {prec} full")
 
 
+def test_layer1_argument_at_fp32_accuracy():
+    """Layer 1 of the BF16/FP16 paths (BF16 MFMAs over three-way splits of
+    weights and coordinates) must be as accurate as the FP32 path's: at depth
+    1 the output is the FP32 first tail of sin of the omega-scaled argument,
+    so any loss in that argument shows directly. Points inside the cube and
+    out to 8 units from its centre (larger arguments); a plain BF16 or a
+    two-way split would miss by 1e-4 and more."""
+    blob = c2_blob(256)
+    ref = oracle.parse_blob(blob)
+    model = sand.load_model(blob, 0)
+    rng = np.random.Generator(np.random.PCG64(57))
+    x = np.concatenate([rng.uniform(-1, 1, size=(49152, 3)),
+                        rng.uniform(-8, 8, size=(16384, 3))]).astype(np.float32)
+    forced = torch.ones(len(x), dtype=torch.uint8, device=DEV)
+    want = oracle.forward(ref, x, np.ones(len(x), dtype=np.int64))
+    err = {}
+    for prec in ("fp32", "bf16", "fp16"):
+        y, _ = run(model, None, x, precision=prec, mode="forced", forced_depth=forced)
+        err[prec] = float(np.abs(y - want).max())
+        say(f"  depth 1, {prec}: max|err| {err[prec]:.3e}")
+    for prec in ("bf16", "fp16"):
+        assert err[prec] <= 2.0 * err["fp32"] + 1e-6, (prec, err)
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp16", "fp32"])
 def test_c3_width336_medium(prec):
     blob = c2_blob(336, seed=1336)
