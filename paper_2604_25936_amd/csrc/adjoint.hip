@@ -81,8 +81,16 @@ __device__ __forceinline__ void pin_out(const typename Tr<PREC>::V (&out)[KS], i
   }
 }
 
-// Forward epilogue that also stashes cos of the sine argument.
-template <int PREC, int KS>
+// What a forward epilogue keeps of cos of the sine argument: FE_STASH
+// writes it to the stash (and the packed activations to out); FE_NONE keeps
+// nothing (layer 1 of a deeper tile: the backward recomputes it); FE_REGS
+// packs the cosines into out instead of the activations (the tile's last
+// layer, whose activations feed nothing and whose cosines the backward
+// needs first).
+enum FwdKeep { FE_STASH, FE_NONE, FE_REGS };
+
+// Forward epilogue: sine, tail partial sums, and the cosines as FwdKeep says.
+template <int PREC, int KS, int KEEP>
 __device__ __forceinline__ void fwd_epilogue(const char* tails, int g, int rb,
                                              const typename Tr<PREC>::Acc& acc,
                                              typename Tr<PREC>::V (&out)[KS], float& s0,
@@ -97,15 +105,37 @@ __device__ __forceinline__ void fwd_epilogue(const char* tails, int g, int rb,
     for (int k = 0; k < 4; ++k) {
       const int e = 4 * i + k;
       h[e] = __builtin_amdgcn_sinf(acc[e]);
-      cs[e] = __builtin_amdgcn_cosf(acc[e]);
+      if constexpr (KEEP != FE_NONE) cs[e] = __builtin_amdgcn_cosf(acc[e]);
       s0 = fmaf(ta[k], h[e], s0);
       s1 = fmaf(tb[k], h[e], s1);
     }
   }
-  T::template store<KS>(out, rb, h);
-  stash_put<PREC>(stash, cs);
+  if constexpr (KEEP == FE_REGS) {
+    T::template store<KS>(out, rb, cs);
+  } else {
+    T::template store<KS>(out, rb, h);
+    if constexpr (KEEP == FE_STASH) stash_put<PREC>(stash, cs);
+  }
   asm volatile("" ::"v"(s0), "v"(s1));
   pin_out<PREC, KS>(out, rb);
+}
+
+// The NR cosines of output block rb that fwd_epilogue<FE_REGS> packed into
+// act, as FP32 (the same 16-bit rounding as the stash).
+template <int PREC, int KS>
+__device__ __forceinline__ void cos_from_regs(const typename Tr<PREC>::V (&act)[KS], int rb,
+                                              float (&cs)[Tr<PREC>::NR]) {
+  using T = Tr<PREC>;
+  if constexpr (T::VB == 16) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cs[k] = (float)act[2 * rb][k];
+      cs[8 + k] = (float)act[2 * rb + 1][k];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < T::NR; ++e) cs[e] = act[4 * rb + e];
+  }
 }
 
 // Backward epilogue of one block: delta' = cos * (acc + u1 a0 + u0 a1).
@@ -114,12 +144,11 @@ __device__ __forceinline__ void fwd_epilogue(const char* tails, int g, int rb,
 template <int PREC, int KS>
 __device__ __forceinline__ void bwd_epilogue(const float* tails, int tstride, int g, int rb,
                                              const typename Tr<PREC>::Acc& acc, float u0,
-                                             float u1, const char* stash,
+                                             float u1, const float (&cs)[Tr<PREC>::NR],
                                              typename Tr<PREC>::V (&out)[KS], bool last,
                                              const char* w1t, float (&gx)[3]) {
   using T = Tr<PREC>;
-  float cs[T::NR], dl[T::NR];
-  stash_get<PREC>(stash, cs);
+  float dl[T::NR];
 #pragma unroll
   for (int i = 0; i < T::NR / 4; ++i) {
     const int row = T::tail_row(i, g);
@@ -168,10 +197,11 @@ __device__ __forceinline__ char* stash_at(char* base, int j, int rb) {
   return base + ((size_t)(j - 1) * Cfg<PREC, WP>::RB + rb) * 64 * stash_lane_bytes<PREC>();
 }
 
-// One forward hidden layer j with stash: in -> out; returns (u0, u1).
+// One forward hidden layer j: in -> out, cosines stashed, or (last: the
+// tile's exit layer) packed into out; returns the tail partial sums.
 template <int PREC, int WP>
 __device__ __forceinline__ void adj_fwd_layer(const char* __restrict__ hidden, char* ring, int wave,
-                                              int lane, int g, int& c, int nc, int j,
+                                              int lane, int g, int& c, int nc, int j, bool last,
                                               const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
                                               typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
                                               char* stash, float& s0, float& s1) {
@@ -195,8 +225,11 @@ __device__ __forceinline__ void adj_fwd_layer(const char* __restrict__ hidden, c
 #pragma unroll
     for (int s = 0; s < C::KS; ++s)
       acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
-    fwd_epilogue<PREC, C::KS>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
-                              stash_at<PREC, WP>(stash, j, rb));
+    if (last)
+      fwd_epilogue<PREC, C::KS, FE_REGS>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1, nullptr);
+    else
+      fwd_epilogue<PREC, C::KS, FE_STASH>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
+                                          stash_at<PREC, WP>(stash, j, rb));
     if (pre) wait_chunk();
     __syncthreads();
     ++c;
@@ -204,10 +237,12 @@ __device__ __forceinline__ void adj_fwd_layer(const char* __restrict__ hidden, c
 }
 
 // One backward layer j (j >= 2): in = delta'_j -> out = delta'_{j-1}, or the
-// input gradient when j == 2.
+// input gradient when j == 2. Layer 1's cosines are recomputed from the
+// point (l1: the layer-1 chunks in LDS): its product is four inputs deep.
 template <int PREC, int WP>
 __device__ __forceinline__ void adj_bwd_layer(const char* __restrict__ bwd, char* ring, int wave,
                                               int lane, int g, int& c, int nc, int d, int j,
+                                              const char* l1, float px, float py, float pz,
                                               const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
                                               typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
                                               char* stash, float v0, float v1, const char* w1t,
@@ -231,8 +266,19 @@ __device__ __forceinline__ void adj_bwd_layer(const char* __restrict__ bwd, char
 #pragma unroll
     for (int s = 0; s < C::KS; ++s)
       acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
-    bwd_epilogue<PREC, C::KS>((const float*)(slot + C::TAIL_OFF_B), T::BM, g, rb, acc, v0, v1,
-                              stash_at<PREC, WP>(stash, j - 1, rb), out, j == 2, w1t, gx);
+    float cs[T::NR];
+    if (j == 2) {
+      typename T::Acc z = {};
+#pragma unroll
+      for (int st = 0; st < T::L1S; ++st)
+        z = T::mma1(T::l1_a(l1 + rb * C::L1C, st, lane), T::l1_b(st, g, px, py, pz), z);
+#pragma unroll
+      for (int e = 0; e < T::NR; ++e) cs[e] = __builtin_amdgcn_cosf(z[e]);
+    } else {
+      stash_get<PREC>(stash_at<PREC, WP>(stash, j - 1, rb), cs);
+    }
+    bwd_epilogue<PREC, C::KS>((const float*)(slot + C::TAIL_OFF_B), T::BM, g, rb, acc, v0, v1, cs,
+                              out, j == 2, w1t, gx);
     if (pre) wait_chunk();
     __syncthreads();
     ++c;
@@ -309,8 +355,12 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
 #pragma unroll
       for (int st = 0; st < T::L1S; ++st)
         acc = T::mma1(T::l1_a(ch, st, lane), T::l1_b(st, g, px, py, pz), acc);
-      fwd_epilogue<PREC, C::KS>(ch + T::L1S * T::L1AB, g, rb, acc, actA, s0, s1,
-                                stash_at<PREC, WP>(stash, 1, rb));
+      if (d == 1)
+        fwd_epilogue<PREC, C::KS, FE_REGS>(ch + T::L1S * T::L1AB, g, rb, acc, actA, s0, s1,
+                                           nullptr);
+      else
+        fwd_epilogue<PREC, C::KS, FE_NONE>(ch + T::L1S * T::L1AB, g, rb, acc, actA, s0, s1,
+                                           nullptr);
     }
     float u0 = T::lane_sum(s0) + q.m.c0[0], u1 = T::lane_sum(s1) + q.m.c1[0];
     float y = fmaf(u0, u1, 0.0f);
@@ -327,9 +377,11 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     }
     for (int j = 2; j <= d; ++j) {
       if (j & 1)
-        adj_fwd_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, j, actB, actA, stash, s0, s1);
+        adj_fwd_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, j, j == d, actB, actA, stash,
+                                s0, s1);
       else
-        adj_fwd_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, j, actA, actB, stash, s0, s1);
+        adj_fwd_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, j, j == d, actA, actB, stash,
+                                s0, s1);
       u0 = T::lane_sum(s0) + q.m.c0[j - 1];
       u1 = T::lane_sum(s1) + q.m.c1[j - 1];
       y = fmaf(u0, u1, y);
@@ -341,16 +393,25 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     if (q.sdf && g == 0 && ok) q.sdf[gi] = y;
 
     // ---------------- backward ----------------
-    // exit tail of layer d: delta'_d = cos_d * (u1 a0 + u0 a1), into actA
+    // exit tail of layer d: delta'_d = cos_d * (u1 a0 + u0 a1), into actA;
+    // cos_d is in layer d's output registers (actA for odd d, actB for even)
     float gx[3] = {0.0f, 0.0f, 0.0f};
     {
       const float* tl = a.tails + (size_t)(d - 1) * 2 * WP;
+      auto exit_tail = [&](const V (&cosv)[C::KS]) {
 #pragma unroll
-      for (int rb = 0; rb < C::RB; ++rb) {
-        const typename T::Acc zero = {};
-        bwd_epilogue<PREC, C::KS>(tl + T::BM * rb, WP, g, rb, zero, u0, u1,
-                                  stash_at<PREC, WP>(stash, d, rb), actA, d == 1, w1t, gx);
-      }
+        for (int rb = 0; rb < C::RB; ++rb) {
+          const typename T::Acc zero = {};
+          float cs[T::NR];
+          cos_from_regs<PREC, C::KS>(cosv, rb, cs);
+          bwd_epilogue<PREC, C::KS>(tl + T::BM * rb, WP, g, rb, zero, u0, u1, cs, actA, d == 1,
+                                    w1t, gx);
+        }
+      };
+      if (d & 1)
+        exit_tail(actA);
+      else
+        exit_tail(actB);
     }
     const int ncb = (d - 1) * C::RB;
     c = 0;
@@ -360,11 +421,13 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       __syncthreads();
     }
     for (int j = d; j >= 2; j -= 2) {
-      adj_bwd_layer<PREC, WP>(a.bwd, ring, wave, lane, g, c, ncb, d, j, actA, actB, stash,
+      adj_bwd_layer<PREC, WP>(a.bwd, ring, wave, lane, g, c, ncb, d, j, l1, px, py, pz, actA,
+                              actB, stash,
                               uw[((j - 2) * NQ + col) * 2], uw[((j - 2) * NQ + col) * 2 + 1], w1t,
                               gx);
       if (j - 1 < 2) break;
-      adj_bwd_layer<PREC, WP>(a.bwd, ring, wave, lane, g, c, ncb, d, j - 1, actB, actA, stash,
+      adj_bwd_layer<PREC, WP>(a.bwd, ring, wave, lane, g, c, ncb, d, j - 1, l1, px, py, pz,
+                              actB, actA, stash,
                               uw[((j - 3) * NQ + col) * 2], uw[((j - 3) * NQ + col) * 2 + 1], w1t,
                               gx);
     }
