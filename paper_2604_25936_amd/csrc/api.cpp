@@ -935,7 +935,8 @@ WorkspaceLayout workspace_layout(int64_t n) {
   w.counts = w.perm + al(4 * (size_t)n);
   w.plan = w.counts + al(nblk * kBuckets * 4);
   w.groups = w.plan + al(sizeof(Plan));
-  w.total = w.groups + al((nblk + kScanGroup - 1) / kScanGroup * kBuckets * 4);
+  w.qcount = w.groups + al((nblk + kScanGroup - 1) / kScanGroup * kBuckets * 4);
+  w.total = w.qcount + al(nblk * 4);
   w.nblk = (int64_t)nblk;
   return w;
 }
@@ -993,8 +994,11 @@ sand_status run_bucketing(sand_model m, sand_depthmap dm, const float* xyz, int6
   const int R = dm ? dm->R : 2;
   hipError_t e;
   mark(0);
+  // the octree's deferred points queue in the permutation buffer, which the
+  // scatter fills only after they are resolved
   if ((e = launch_lookup_count(xyz, n, map, R, far, oct, o.forced_depth, o.mode, m->L, o.max_depth, depth,
-                               sdf, grad, counts, s)) != hipSuccess)
+                               sdf, grad, counts, perm, (int32_t*)(ws + w.qcount), s)) !=
+      hipSuccess)
     return device_fail(e, "lookup launch");
   mark(1);
   if ((e = launch_scan(counts, w.nblk, m->L, tile_q, plan, (int32_t*)(ws + w.groups), s)) !=

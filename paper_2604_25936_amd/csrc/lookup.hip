@@ -45,7 +45,11 @@ __device__ __forceinline__ int cell_index(float x, float s, int half) {
 // rank word and the word holding the child's bit are loaded together: the
 // child's slot is 8 rank(parent) + child, and the child is internal when its
 // bit is set (only below level D). A leaf's depth and value are loaded last.
-template <int P>
+// DEFER: points whose level-K cell is internal are not descended; their
+// depth is set to kDeferred for a second pass (k_oct_deferred).
+constexpr int kDeferred = 255;
+
+template <int P, bool DEFER = false>
 __device__ __forceinline__ void octree_leaves(const OctreeArgs& o, const float (&x)[P],
                                               const float (&y)[P], const float (&z)[P],
                                               int (&d)[P], float (&v)[P]) {
@@ -92,12 +96,14 @@ __device__ __forceinline__ void octree_leaves(const OctreeArgs& o, const float (
       live[i] = e[i].x == kOctInternal;
       w[i] = 0;
       if (live[i]) {
-        w[i] = bitsK[p[i] >> 6];
+        if constexpr (DEFER) d[i] = kDeferred;
+        else w[i] = bitsK[p[i] >> 6];
       } else {
         d[i] = (int)e[i].x;
         v[i] = __uint_as_float(e[i].y);
       }
     }
+    if constexpr (DEFER) return;
   } else {
     const uint64_t w0 = o.bits[0][0];
 #pragma unroll
@@ -197,10 +203,12 @@ __device__ __forceinline__ void lookup_block(
     int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
     const uint8_t* __restrict__ forced, int mode, int L, int max_depth,
     uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
-    int32_t* __restrict__ counts) {
+    int32_t* __restrict__ counts, int32_t* __restrict__ queue, int32_t* __restrict__ qcount) {
   __shared__ int hist[kBuckets];
+  __shared__ int nq;
   const int t = threadIdx.x;
   if (t < kBuckets) hist[t] = 0;
+  if (t == 0) nq = 0;
   const int64_t base = blk * kLookupChunk;
   const int half = R >> 1;
   const float s = (float)half;
@@ -244,7 +252,10 @@ __device__ __forceinline__ void lookup_block(
     // the map's depth (and, for an octree, the leaf's value) of every point;
     // FORCED mode keeps the map's far value for points forced to depth 0
     if (oct != nullptr) {
-      if (mode != 1) octree_leaves<kPP>(*oct, x, y, z, d, farv);
+      if (mode == 0 && queue)
+        octree_leaves<kPP, true>(*oct, x, y, z, d, farv);
+      else if (mode != 1)
+        octree_leaves<kPP>(*oct, x, y, z, d, farv);
     } else if (map != nullptr) {
 #pragma unroll
       for (int i = 0; i < kPP; ++i)
@@ -265,9 +276,37 @@ __device__ __forceinline__ void lookup_block(
         d[i] = dd > L ? L : dd;
       }
     }
+    // points left for the octree's second pass: queued, kept out of this
+    // pass's histogram, their depth byte written there
+    bool deferred[kPP];
+#pragma unroll
+    for (int i = 0; i < kPP; ++i) deferred[i] = queue && d[i] == kDeferred && q0 + i < n;
+    if (queue) {
+      const int lane = t & 63;
+      uint64_t m[kPP];
+      int tot = 0;
+#pragma unroll
+      for (int i = 0; i < kPP; ++i) {
+        m[i] = __ballot(deferred[i]);
+        tot += __popcll(m[i]);
+      }
+      if (tot > 0) {
+        // the chunk's own stretch of the queue: no global atomics
+        int qb = 0;
+        if (lane == 0) qb = atomicAdd(&nq, tot);
+        qb = __shfl(qb, 0);
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        int32_t* cq = queue + base;
+#pragma unroll
+        for (int i = 0; i < kPP; ++i) {
+          if (deferred[i]) cq[qb + __popcll(m[i] & below)] = (int32_t)(q0 + i);
+          qb += __popcll(m[i]);
+        }
+      }
+    }
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {
-      if (max_depth > 0 && d[i] > max_depth) d[i] = max_depth;
+      if (!deferred[i] && max_depth > 0 && d[i] > max_depth) d[i] = max_depth;
       if (q0 + i >= n) d[i] = 0;
       if (d[i] == 0 && oct == nullptr && far != nullptr && cell[i] >= 0) farv[i] = far[cell[i]];
     }
@@ -294,13 +333,14 @@ __device__ __forceinline__ void lookup_block(
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {
       const int64_t q = q0 + i;
-      valid[i] = q < n;
+      valid[i] = q < n && !deferred[i];
       if (valid[i] && d[i] == 0 && grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
     }
     wave_histogram_n<kPP>(d, valid, hist);
   }
   __syncthreads();
   if (t < kBuckets) counts[blk * kBuckets + t] = hist[t];
+  if (queue && t == 0) qcount[blk] = nq;
 }
 
 __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
@@ -308,9 +348,9 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
     int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
     const uint8_t* __restrict__ forced, int mode, int L, int max_depth,
     uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
-    int32_t* __restrict__ counts) {
+    int32_t* __restrict__ counts, int32_t* __restrict__ queue, int32_t* __restrict__ qcount) {
   lookup_block(blockIdx.x, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf,
-               grad, counts);
+               grad, counts, queue, qcount);
 }
 
 constexpr int kScanThreads = 1024;
@@ -563,7 +603,7 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_batch(const BatchReq*
   const int r = find_request(reqs, nreq, blockIdx.x);
   const BatchReq& q = reqs[r];
   lookup_block((int64_t)blockIdx.x - q.blk0, q.xyz, q.n, q.map, q.R, q.far, q.oct, nullptr, 0,
-               q.L, max_depth, q.depth, q.sdf, nullptr, q.counts);
+               q.L, max_depth, q.depth, q.sdf, nullptr, q.counts, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_batch(BatchReq* __restrict__ reqs,
@@ -591,6 +631,48 @@ __global__ void k_batch_tiles(BatchReq* __restrict__ reqs, int nreq,
   *total = run;
 }
 
+// Second pass of an octree lookup: the points whose level-K cell is
+// internal, queued per 4096-point chunk (qcount[c] of them at queue + 4096 c),
+// one thread each, descend from the root (no resolved point waits for
+// them); one wavefront per chunk. Writes their depth, far value and zero
+// gradient, and adds them to their chunk's histogram with one atomic per
+// distinct depth of a wavefront.
+__global__ __launch_bounds__(64) void k_oct_deferred(
+    const float* __restrict__ xyz, const OctreeArgs* __restrict__ oct, int max_depth,
+    const int32_t* __restrict__ queue, const int32_t* __restrict__ qcount,
+    uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
+    int32_t* __restrict__ counts) {
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  const int cnt = qcount[c];
+  for (int b0 = 0; b0 < cnt; b0 += 64) {
+    const int idx = b0 + (int)threadIdx.x;
+    const bool active = idx < cnt;
+    int d1 = -1;
+    if (active) {
+      const int64_t q = queue[c * kLookupChunk + idx];
+      float x[1] = {xyz[3 * q]}, y[1] = {xyz[3 * q + 1]}, z[1] = {xyz[3 * q + 2]}, v[1];
+      int d[1];
+      octree_leaves<1>(*oct, x, y, z, d, v);
+      if (max_depth > 0 && d[0] > max_depth) d[0] = max_depth;
+      depth[q] = (uint8_t)d[0];
+      if (d[0] == 0) {
+        if (sdf) sdf[q] = v[0];
+        if (grad) grad[3 * q] = grad[3 * q + 1] = grad[3 * q + 2] = 0.0f;
+      }
+      d1 = d[0];
+    }
+    uint64_t todo = __ballot(active);
+    while (todo) {
+      const int lead = __ffsll((long long)todo) - 1;
+      const int ld = __shfl(d1, lead);
+      const uint64_t same = __ballot(active && d1 == ld);
+      if (lane == lead) atomicAdd(&counts[c * kBuckets + ld], __popcll(same));
+      todo &= ~same;
+    }
+  }
+}
+
 __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -602,10 +684,17 @@ __global__ void k_fill_u8(uint8_t* p, int64_t n, uint8_t v) {
 hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map, int R,
                                const float* far, const OctreeArgs* oct, const uint8_t* forced,
                                int mode, int L, int max_depth, uint8_t* depth, float* sdf,
-                               float* grad, int32_t* counts, hipStream_t s) {
+                               float* grad, int32_t* counts, int32_t* queue, int32_t* qcount,
+                               hipStream_t s) {
   const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
+  const bool two_pass = oct != nullptr && mode == 0 && queue != nullptr && qcount != nullptr;
   hipLaunchKernelGGL(k_lookup_count, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, xyz,
-                     n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad, counts);
+                     n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad, counts,
+                     two_pass ? queue : nullptr, two_pass ? qcount : nullptr);
+  if (two_pass) {
+    hipLaunchKernelGGL(k_oct_deferred, dim3((unsigned)nblk), dim3(64), 0, s, xyz, oct,
+                       max_depth, queue, qcount, depth, sdf, grad, counts);
+  }
   return hipGetLastError();
 }
 

@@ -49,7 +49,7 @@ struct DeviceGuard {
 
 // Byte offsets of the per-query scratch regions.
 struct WorkspaceLayout {
-  size_t depth, perm, counts, plan, groups, total;
+  size_t depth, perm, counts, plan, groups, qcount, total;
   int64_t nblk;
 };
 WorkspaceLayout workspace_layout(int64_t n);

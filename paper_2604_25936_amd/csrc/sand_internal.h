@@ -170,11 +170,15 @@ struct AdjointArgs {
 };
 
 // ---- launchers (defined in the .hip files) ----
+// queue [n] and qcount [ceil(n / kLookupChunk)]: scratch of the octree's
+// two-pass adaptive lookup (points below the dense index are queued per
+// chunk and descended in a second kernel), or null
 hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map,
                                int R, const float* far, const OctreeArgs* oct,
                                const uint8_t* forced,
                                int mode, int L, int max_depth, uint8_t* depth,
-                               float* sdf, float* grad, int32_t* counts, hipStream_t s);
+                               float* sdf, float* grad, int32_t* counts, int32_t* queue,
+                               int32_t* qcount, hipStream_t s);
 // groups: scratch of ceil(nblk / kScanGroup) * kBuckets int32, used when
 // nblk exceeds one scan workgroup's threads
 hipError_t launch_scan(int32_t* counts, int64_t nblk, int L, int tile_q,
