@@ -17,7 +17,11 @@
 //      (ballots + popcounts below the lane) gives its slot in the
 //      permutation.
 // Every thread takes four consecutive points per round, so a wavefront's
-// coordinate loads cover 3 KB of contiguous memory in 16-byte pieces.
+// coordinate loads cover 3 KB of contiguous memory in 16-byte pieces. With
+// an octree, the first step resolves points through the tree's dense index
+// only and queues the rest per chunk; k_oct_deferred descends those (one
+// wavefront per chunk) and adds them to the chunk histograms before the
+// scan, so no resolved point waits on another point's descent.
 // Batched variants run the same bodies for several queries in one launch
 // (each lookup block belongs to one query; one scan workgroup per query).
 
@@ -198,6 +202,7 @@ __device__ __forceinline__ void wave_histogram_n(const int (&d)[P], const bool (
 constexpr int kPP = 4;
 constexpr int kQuadRounds = kLookupChunk / (kLookupThreads * kPP);
 
+template <bool DEFER>
 __device__ __forceinline__ void lookup_block(
     int64_t blk, const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
     int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
@@ -252,7 +257,7 @@ __device__ __forceinline__ void lookup_block(
     // the map's depth (and, for an octree, the leaf's value) of every point;
     // FORCED mode keeps the map's far value for points forced to depth 0
     if (oct != nullptr) {
-      if (mode == 0 && queue)
+      if (DEFER)
         octree_leaves<kPP, true>(*oct, x, y, z, d, farv);
       else if (mode != 1)
         octree_leaves<kPP>(*oct, x, y, z, d, farv);
@@ -280,8 +285,8 @@ __device__ __forceinline__ void lookup_block(
     // pass's histogram, their depth byte written there
     bool deferred[kPP];
 #pragma unroll
-    for (int i = 0; i < kPP; ++i) deferred[i] = queue && d[i] == kDeferred && q0 + i < n;
-    if (queue) {
+    for (int i = 0; i < kPP; ++i) deferred[i] = DEFER && d[i] == kDeferred && q0 + i < n;
+    if constexpr (DEFER) {
       const int lane = t & 63;
       uint64_t m[kPP];
       int tot = 0;
@@ -340,17 +345,19 @@ __device__ __forceinline__ void lookup_block(
   }
   __syncthreads();
   if (t < kBuckets) counts[blk * kBuckets + t] = hist[t];
-  if (queue && t == 0) qcount[blk] = nq;
+  if (DEFER && t == 0) qcount[blk] = nq;
 }
 
+// DEFER: the octree's two-pass adaptive lookup (first pass)
+template <bool DEFER>
 __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
     const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
     int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
     const uint8_t* __restrict__ forced, int mode, int L, int max_depth,
     uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
     int32_t* __restrict__ counts, int32_t* __restrict__ queue, int32_t* __restrict__ qcount) {
-  lookup_block(blockIdx.x, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf,
-               grad, counts, queue, qcount);
+  lookup_block<DEFER>(blockIdx.x, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth,
+                      sdf, grad, counts, queue, qcount);
 }
 
 constexpr int kScanThreads = 1024;
@@ -602,7 +609,7 @@ __global__ __launch_bounds__(kLookupThreads) void k_lookup_batch(const BatchReq*
                                                                  int nreq, int max_depth) {
   const int r = find_request(reqs, nreq, blockIdx.x);
   const BatchReq& q = reqs[r];
-  lookup_block((int64_t)blockIdx.x - q.blk0, q.xyz, q.n, q.map, q.R, q.far, q.oct, nullptr, 0,
+  lookup_block<false>((int64_t)blockIdx.x - q.blk0, q.xyz, q.n, q.map, q.R, q.far, q.oct, nullptr, 0,
                q.L, max_depth, q.depth, q.sdf, nullptr, q.counts, nullptr, nullptr);
 }
 
@@ -688,9 +695,14 @@ hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map, 
                                hipStream_t s) {
   const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
   const bool two_pass = oct != nullptr && mode == 0 && queue != nullptr && qcount != nullptr;
-  hipLaunchKernelGGL(k_lookup_count, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s, xyz,
-                     n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad, counts,
-                     two_pass ? queue : nullptr, two_pass ? qcount : nullptr);
+  if (two_pass)
+    hipLaunchKernelGGL(k_lookup_count<true>, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s,
+                       xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad,
+                       counts, queue, qcount);
+  else
+    hipLaunchKernelGGL(k_lookup_count<false>, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s,
+                       xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad,
+                       counts, nullptr, nullptr);
   if (two_pass) {
     hipLaunchKernelGGL(k_oct_deferred, dim3((unsigned)nblk), dim3(64), 0, s, xyz, oct,
                        max_depth, queue, qcount, depth, sdf, grad, counts);

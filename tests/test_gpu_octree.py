@@ -122,6 +122,40 @@ def test_c2_model_tree():
     assert np.abs(yb - y).max() <= 2 * TOL["bf16"]
 
 
+def test_tree_lod_clamp_and_gradient():
+    """Through a tree, a max_depth clamp and a gradient query: the points
+    below the tree's dense index are resolved in a second pass, which must
+    clamp their depth and give far points a zero gradient like the first."""
+    D, s, r = 5, 2, 0.3
+    say(f"case: 3x10 plain-init model, octree D={D}, LOD clamp 2 and gradient, fp32")
+    blob = synth.write_blob(synth.siren_tmlp(67, 3, 10, tails="mult", scale="plain"))
+    ref = oracle.parse_blob(blob)
+    model = sand.load_model(blob, 0)
+    dm, _ = sand.construct_octree(model, D=D, s=s, r=r)
+    rng = np.random.Generator(np.random.PCG64(5))
+    x = rng.uniform(-1, 1, size=(30000, 3)).astype(np.float32)
+    xyz = torch.from_numpy(x).to(DEV)
+    y, d = gpu_query(model, dm, x)
+    dl = torch.full((len(x),), 255, dtype=torch.uint8, device=DEV)
+    yl = sand.query(model, dm, xyz, precision="fp32", max_depth=2, depth_out=dl).cpu().numpy()
+    dl = dl.cpu().numpy().astype(np.int64)
+    say(f"  depths {np.bincount(d, minlength=4).tolist()} -> clamped {np.bincount(dl, minlength=4).tolist()}")
+    assert (d > 2).any() and (d == 0).any()
+    assert np.array_equal(dl, np.minimum(d, 2))
+    far = d == 0
+    assert np.array_equal(yl[far], y[far].astype(np.float32))
+    want = oracle.forward(ref, x[~far].astype(np.float64), dl[~far])
+    assert np.abs(yl[~far] - want).max() <= TOL["fp32"]
+    g = torch.empty((len(x), 3), dtype=torch.float32, device=DEV)
+    sand.query_grad(model, dm, xyz, grad_out=g, precision="fp32")
+    g = g.cpu().numpy().astype(np.float64)
+    assert not g[far].any(), "far points must have a zero gradient"
+    gw = oracle.gradient(ref, x[~far].astype(np.float64), d[~far])
+    err = np.linalg.norm(g[~far] - gw, axis=1) / (np.linalg.norm(gw, axis=1) + 1.0)
+    say(f"  gradient: {int((~far).sum())} near points, max rel err {err.max():.2e}")
+    assert err.max() <= 1e-4
+
+
 def constant_blob(c, L=3, W=16):
     p = synth.siren_tmlp(9, L, W, tails="mult", scale="plain")
     p["tails"] = [{"kind": 0, "a": np.zeros(W), "c": float(c)}] + [
