@@ -3,8 +3,9 @@
 // Requests (model, map, host point set) are queued by sand_server_submit.
 // A scheduler thread admits them first-in first-out while the device bytes
 // they need fit a fixed HBM arena (the budget), and whenever one of the
-// n_streams launch slots is free it launches every admitted request of one
-// padded width as one batch: the point sets are copied in, one lookup /
+// n_streams launch slots is free it launches the admitted requests of one
+// padded width, in order and up to a total of 2M points (a larger request
+// alone), as one batch: the point sets are copied in, one lookup /
 // bucketing launch and one persistent T-MLP launch cover all of them (each
 // tile knows its query and model), and the results are copied back. A
 // request that arrives while batches are running joins the next batch as
@@ -36,6 +37,10 @@ double now_s() {
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kMaxBatchRequests = 1024;
+// Points one batch gathers before it closes (a larger request still forms a
+// batch of its own): a small request does not wait for the copies and
+// evaluation of a multi-million-point one launched with it.
+constexpr int64_t kBatchPointCap = int64_t(1) << 21;
 
 // Device bytes one request holds from admission to completion.
 struct ReqLayout {
@@ -243,10 +248,15 @@ void sand_server_s::run() {
       any_busy |= s->busy;
     }
     if (!admitted.empty() && free_slot) {
+      // admitted requests of the head's padded width, in order, up to the
+      // point cap (the head always goes)
       const int WP = admitted.front()->model->WP;
+      int64_t points = 0;
       for (auto it = admitted.begin();
            it != admitted.end() && (int)free_slot->reqs.size() < kMaxBatchRequests;) {
-        if ((*it)->model->WP == WP) {
+        const bool fits = free_slot->reqs.empty() || points + (*it)->n <= kBatchPointCap;
+        if ((*it)->model->WP == WP && fits) {
+          points += (*it)->n;
           free_slot->reqs.push_back(*it);
           it = admitted.erase(it);
         } else {
