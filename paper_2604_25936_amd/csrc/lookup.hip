@@ -53,6 +53,14 @@ __device__ __forceinline__ int cell_index(float x, float s, int half) {
 // depth is set to kDeferred for a second pass (k_oct_deferred).
 constexpr int kDeferred = 255;
 
+// Bit i of v (v < 2^10) moved to bit 3i.
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  return (v | (v << 2)) & 0x09249249u;
+}
+
 template <int P, bool DEFER = false>
 __device__ __forceinline__ void octree_leaves(const OctreeArgs& o, const float (&x)[P],
                                               const float (&y)[P], const float (&z)[P],
@@ -82,15 +90,13 @@ __device__ __forceinline__ void octree_leaves(const OctreeArgs& o, const float (
   }
   if (K > 0) {
     // the dense index of level K: the Morton code of the point's level-K cell
+    // (the top K bits of each cell index, interleaved x, y, z from the top)
     uint2 e[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      uint32_t code = 0;
-      for (int l = 1; l <= K; ++l) {
-        const int sh = D - l;
-        code = 8u * code + ((((ix[i] >> sh) & 1) << 2) | (((iy[i] >> sh) & 1) << 1) |
-                            ((iz[i] >> sh) & 1));
-      }
+      const int sh = D - K;
+      const uint32_t code = (spread3((uint32_t)ix[i] >> sh) << 2) |
+                            (spread3((uint32_t)iy[i] >> sh) << 1) | spread3((uint32_t)iz[i] >> sh);
       p[i] = code;
       e[i] = o.top[code];
     }
