@@ -78,6 +78,28 @@ def test_mix_equals_alone(models, prec):
     srv.close()
 
 
+def test_batch_point_cap(models):
+    """A batch closes at 2M points: a request above that runs alone, the
+    others share batches up to it; every result equals the query alone."""
+    sizes = [2_500_000, 800_000, 800_000, 800_000, 3, 5000, 700_000, 17]
+    say(f"case: batch point cap, requests of {sizes} points, bf16")
+    srv = sand.Server(0, budget_bytes=1 << 30, precision="bf16", n_streams=3)
+    reqs = []
+    for i, n in enumerate(sizes):
+        k = i % 4
+        x = request_points(k, n, seed=300 + i)
+        y = np.full(n, np.nan, dtype=np.float32)
+        reqs.append((k, x, y, srv.submit(models[k][1], models[k][3], x, y)))
+    stats = [srv.wait(t) for (_, _, _, t) in reqs]
+    info = srv.stats()
+    say(f"  batches={info['batches']} batch sizes {[st['batch_size'] for st in stats]}")
+    assert stats[0]["batch_size"] == 1, "a request above the cap must run alone"
+    assert info["batches"] >= 3
+    for (k, x, y, _) in reqs:
+        assert np.array_equal(y, alone(models[k][1], models[k][3], x, "bf16"))
+    srv.close()
+
+
 def test_budget_admission_and_fifo(models):
     budget = 64 << 20
     srv = sand.Server(0, budget_bytes=budget, precision="bf16", n_streams=2)
