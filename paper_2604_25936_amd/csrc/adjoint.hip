@@ -312,7 +312,17 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
                 lane * stash_lane_bytes<PREC>();
   float* uw = ust + wave * kMaxLayers * NQ * 2;   // [layer][point][2]
 
-  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+  // Tiles (deepest first) are drawn one at a time from a counter, so a
+  // workgroup that drew deep tiles draws fewer and none ends a whole deep
+  // tile after the others (a static round robin gave some workgroups one
+  // depth-L tile more).
+  __shared__ uint32_t drawn;
+  for (;;) {
+    if (tid == 0) drawn = atomicAdd(a.next_tile, 1u);
+    __syncthreads();
+    const int64_t tile = drawn;
+    __syncthreads();
+    if (tile >= total) break;
     int d;
     int64_t start, cnt;
     if (q.plan) {

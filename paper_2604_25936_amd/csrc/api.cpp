@@ -1277,7 +1277,12 @@ extern "C" sand_status sand_query_grad(sand_model m, sand_depthmap dm, const flo
       const int64_t tiles = (n + adjoint_tile_points(prec) - 1) / adjoint_tile_points(prec);
       if (tiles < grid) grid = (int)tiles;
     }
-    if ((e = launch_adjoint(prec, aa, grid, s)) != hipSuccess) st = device_fail(e, "adjoint launch");
+    // the tile counter: the octree lookup's queue lengths, free once bucketing is done
+    aa.next_tile = (uint32_t*)(ws + workspace_layout(n).qcount);
+    if ((e = launch_fill_u8((uint8_t*)aa.next_tile, 4, 0, s)) != hipSuccess)
+      st = device_fail(e, "tile counter fill launch");
+    else if ((e = launch_adjoint(prec, aa, grid, s)) != hipSuccess)
+      st = device_fail(e, "adjoint launch");
   }
   if (owned) (void)hipFreeAsync(ws, s);
   return st;

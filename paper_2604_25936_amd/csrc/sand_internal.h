@@ -167,6 +167,7 @@ struct AdjointArgs {
   float* grad;             // [n][3]
   char* stash;             // per-workgroup cosine stash
   size_t stash_wg;         // stash bytes per workgroup
+  uint32_t* next_tile;     // tile counter, zero at launch (tiles are drawn one at a time)
 };
 
 // ---- launchers (defined in the .hip files) ----
