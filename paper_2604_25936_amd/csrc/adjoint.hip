@@ -302,12 +302,16 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
   const int g = T::grp(lane), col = T::col(lane);
   const QueryArgs& q = a.q;
 
+  __shared__ Plan splan;   // the plan's bucket bounds, read per tile
   for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)q.m.chunks)[i];
   for (int i = tid; i < A::W1T / 16; i += C::NT) ((uint4*)w1t)[i] = ((const uint4*)a.w1t)[i];
+  if (q.plan)
+    for (int i = tid; i < (int)(sizeof(Plan) / 8); i += C::NT)
+      ((int64_t*)&splan)[i] = ((const int64_t*)q.plan)[i];
   __syncthreads();
   const char* hidden = q.m.chunks + C::L1B;
   const int L = q.m.L;
-  const int64_t total = q.plan ? q.plan->total_tiles : (q.n + Q - 1) / Q;
+  const int64_t total = q.plan ? splan.total_tiles : (q.n + Q - 1) / Q;
   char* stash = a.stash + (size_t)blockIdx.x * a.stash_wg + (size_t)wave * L * A::STASH_WL +
                 lane * stash_lane_bytes<PREC>();
   float* uw = ust + wave * kMaxLayers * NQ * 2;   // [layer][point][2]
@@ -328,13 +332,13 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     if (q.plan) {
       d = 1;
       for (int dd = L; dd >= 1; --dd)
-        if (tile < q.plan->tile_end[dd]) {
+        if (tile < splan.tile_end[dd]) {
           d = dd;
           break;
         }
-      const int64_t local = tile - q.plan->tile_end[d + 1];
-      start = q.plan->start[d] + local * Q;
-      cnt = q.plan->count[d] - local * Q;
+      const int64_t local = tile - splan.tile_end[d + 1];
+      start = splan.start[d] + local * Q;
+      cnt = splan.count[d] - local * Q;
     } else {
       d = q.full_depth;
       start = tile * Q;
