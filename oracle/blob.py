@@ -2,7 +2,8 @@
 
 Reads the version-1 little-endian blob: a 64-byte header (magic b"SANDTMLP",
 u32 version, u32 L, u32 W, u32 input dim = 3, f32 omega of layer 1, f32 omega
-of layers 2..L, u8 tail kind per layer, 16 reserved bytes) followed by the
+of layers 2..L, u8 tail kind per layer, u8 activation (0 = SIREN sine,
+1 = FINER variable-periodic sine), 15 reserved bytes) followed by the
 float32 parameters W_1, b_1, (W_j, b_j) for j = 2..L, then each tail in layer
 order: linear (a, c) or multiplicative (a0, c0, a1, c1). Eq. 2 defines the
 layers and tails; Eq. 3 the multiplicative tail.
@@ -26,6 +27,9 @@ def parse_blob(data):
     kinds = list(data[32:32 + L])
     if any(k not in (0, 1) for k in kinds):
         raise ValueError("bad tail kind")
+    if data[48] not in (0, 1):
+        raise ValueError("bad activation")
+    activation = ("sine", "finer")[data[48]]
     vals = np.frombuffer(data, dtype="<f4", offset=64).astype(np.float64)
     pos = 0
 
@@ -56,4 +60,5 @@ def parse_blob(data):
     if pos != vals.size:
         raise ValueError("blob has trailing bytes")
     omegas = [float(np.float32(om1))] + [float(np.float32(omh))] * (L - 1)
-    return {"L": L, "W": W, "omega": omegas, "W_": Ws, "b_": bs, "tails": tails}
+    return {"L": L, "W": W, "omega": omegas, "W_": Ws, "b_": bs, "tails": tails,
+            "activation": activation}

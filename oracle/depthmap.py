@@ -24,7 +24,7 @@ distance from a voxel's centre to the surface is at most half the voxel's
 diagonal, against the shape; the generators in synth/ do the same test
 against the analytic scene).
 
-Pins (tests/test_oracle_depthmap.py): required_depth against a pure-Python
+Pins (tests/oracle_pins.py): required_depth against a pure-Python
 loop over the definition on adversarial y rows (ties at r, zeros, sign
 flips); invariants (range, monotone in r, truncated models whose tails
 beyond layer k vanish give d <= k, with equality where the k-th tail moves

@@ -12,7 +12,7 @@ output t_i (y_i = y_{i-1} + t_i, Eq. 2). Reading: the test starts at layer
 then the level-of-detail clamp d <- min(d, max_depth) when max_depth > 0,
 and the output is y_d (Eq. 2).
 
-Pins (tests/test_oracle_dynamic.py): exit_from_tails against a pure-Python
+Pins (tests/oracle_pins.py): exit_from_tails against a pure-Python
 loop over the definition on lattice values (exact ties at r, zeros,
 negative tails); hand cases; monotone in r; tails computed per layer equal
 the differences of the accumulated outputs; a model whose tails beyond
@@ -22,6 +22,7 @@ model.
 
 import numpy as np
 
+from . import tmlp
 from .tmlp import _tail, forward
 
 
@@ -31,7 +32,7 @@ def tails(model, xyz):
     out = np.zeros((h.shape[0], model["L"]), dtype=np.float64)
     for j in range(1, model["L"] + 1):
         z = h @ model["W_"][j - 1].T + model["b_"][j - 1]
-        h = np.sin(model["omega"][j - 1] * z)
+        h = tmlp.activation(model, j, z)
         out[:, j - 1] = _tail(model["tails"][j - 1], h)
     return out
 

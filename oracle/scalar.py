@@ -3,7 +3,8 @@
 One point at a time, with math.sin and correctly-rounded math.fsum dot
 products, no numpy: a brute-force counterpart for tiny networks that shares
 no array code with ``oracle.tmlp``. Eq. 2 (layers, tails, accumulation) and
-Eq. 3 (multiplicative tail).
+Eq. 3 (multiplicative tail); the activation is SIREN's sin(omega z) or
+FINER's sin(omega (|z| + 1) z).
 """
 
 import math
@@ -20,6 +21,12 @@ def tail_value(tail, h):
     return (_dot(a0, h) + float(c0)) * (_dot(a1, h) + float(c1))
 
 
+def _sigma(kind, om, v):
+    if kind == "finer":
+        return math.sin(om * (abs(v) + 1.0) * v)
+    return math.sin(om * v)
+
+
 def forward_point(model, x, d):
     """y_d at one point ``x`` (3 floats) for exit depth d >= 1."""
     h = [float(v) for v in x]
@@ -28,6 +35,7 @@ def forward_point(model, x, d):
         Wj = model["W_"][j - 1]
         bj = model["b_"][j - 1]
         om = model["omega"][j - 1]
-        h = [math.sin(om * (_dot(Wj[u], h) + float(bj[u]))) for u in range(len(bj))]
+        h = [_sigma(model["activation"], om, _dot(Wj[u], h) + float(bj[u]))
+             for u in range(len(bj))]
         terms.append(tail_value(model["tails"][j - 1], h))
     return math.fsum(terms)

@@ -13,17 +13,23 @@ What is computed, per query point x (FP32 or FP64 coordinates, widened exactly t
 3. d = 0 marks a far-field cell: the value stored for that cell is returned
    and no network runs (Sec. 3.2, Eq. 7; Sec. 3.4).
 4. Otherwise the T-MLP of Eq. 2 runs to layer d: h_0 = x,
-   h_j = sin(omega_j (W_j h_{j-1} + b_j)) (the SIREN activation), tail t_j
-   from h_j -- linear a.h + c, or for the multiplicative design of Eq. 3
+   z_j = W_j h_{j-1} + b_j, h_j = sigma_j(z_j), tail t_j from h_j -- linear a.h + c, or for the multiplicative design of Eq. 3
    (a0.h + c0)(a1.h + c1) -- and the output is the accumulated
    y_d = t_1 + ... + t_d (Eq. 2; the overview figure's caption: the
    accumulated output up to the exit depth is the prediction).
+   The activation sigma_j is the backbone's (Sec. 4.1 runs SAND on SIREN and
+   on FINER and restates neither; both definitions are their own papers'):
+     sine  (SIREN):  sigma_j(z) = sin(omega_j z);
+     finer (FINER, variable-periodic sine): sigma_j(z) = sin(omega_j (|z| + 1) z).
 5. Input gradient of y_d with d held fixed (the map is piecewise constant):
    reverse accumulation from the exit tail,
-     g_d = dt_d/dh_d,  delta_j = omega_j cos(omega_j z_j) * g_j,
+     g_d = dt_d/dh_d,  delta_j = sigma_j'(z_j) * g_j,
      g_{j-1} = W_j^T delta_j + dt_{j-1}/dh_{j-1},  grad_x = W_1^T delta_1,
-   with dt/dh = a (linear) or (a1.h + c1) a0 + (a0.h + c0) a1 (Eq. 3).
-   A far-field point's value is constant within its cell: gradient 0.
+   with dt/dh = a (linear) or (a1.h + c1) a0 + (a0.h + c0) a1 (Eq. 3), and
+   sigma_j'(z) = omega_j cos(omega_j z) (sine) or
+   omega_j (2|z| + 1) cos(omega_j (|z| + 1) z) (finer: d/dz of (|z| + 1) z
+   is 2|z| + 1). A far-field point's value is constant within its cell:
+   gradient 0.
 
 Pins (tests/test_oracle_pins.py): the cell rule against exact rational box
 membership; forward against the textbook MLP of Eq. 1 (intermediate tails
@@ -31,7 +37,10 @@ zeroed) built from torch.nn layers; the quadratic-form identity of the
 appendix for the multiplicative tail; truncation (exit at k equals the
 k-layer network at full depth); an all-L map equals full depth; a pure-Python
 scalar twin on tiny inputs; 50-digit mpmath spot values; the gradient against
-torch autograd and against central differences.
+torch autograd and against central differences. The FINER activation:
+its zeros and extrema at the roots of omega (|z| + 1) z = k pi / 2 solved
+at 50 digits (odd in z), its slope against central differences, and the
+scalar twin, mpmath, truncation and gradient pins on FINER models.
 """
 
 import numpy as np
@@ -68,6 +77,22 @@ def lookup_depth(xyz, dmap, L, mode=MODE_ADAPTIVE, forced=None, max_depth=0):
     if max_depth > 0:
         d = np.minimum(d, max_depth)
     return d
+
+
+def activation(model, j, z):
+    """h_j = sigma_j(z_j) for the pre-activation z_j of layer j (step 4)."""
+    om = model["omega"][j - 1]
+    if model["activation"] == "finer":
+        return np.sin(om * (np.abs(z) + 1.0) * z)
+    return np.sin(om * z)
+
+
+def activation_slope(model, j, z):
+    """sigma_j'(z_j), the derivative of the activation (step 5)."""
+    om = model["omega"][j - 1]
+    if model["activation"] == "finer":
+        return om * (2.0 * np.abs(z) + 1.0) * np.cos(om * (np.abs(z) + 1.0) * z)
+    return om * np.cos(om * z)
 
 
 def _tail(t, h):
@@ -108,7 +133,7 @@ def forward(model, xyz, d, far=None):
         if rows.size == 0:
             break
         z = h @ model["W_"][j - 1].T + model["b_"][j - 1]
-        h = np.sin(model["omega"][j - 1] * z)
+        h = activation(model, j, z)
         y[rows] += _tail(model["tails"][j - 1], h)
         keep = d[rows] > j
         rows, h = rows[keep], h[keep]
@@ -122,7 +147,7 @@ def forward_all_tails(model, xyz):
     y = np.zeros(h.shape[0], dtype=np.float64)
     for j in range(1, model["L"] + 1):
         z = h @ model["W_"][j - 1].T + model["b_"][j - 1]
-        h = np.sin(model["omega"][j - 1] * z)
+        h = activation(model, j, z)
         y = y + _tail(model["tails"][j - 1], h)
         out[:, j - 1] = y
     return out
@@ -141,11 +166,10 @@ def gradient(model, xyz, d):
         for j in range(1, k + 1):
             z = hs[-1] @ model["W_"][j - 1].T + model["b_"][j - 1]
             zs.append(z)
-            hs.append(np.sin(model["omega"][j - 1] * z))
+            hs.append(activation(model, j, z))
         g = np.array(_tail_grad(model["tails"][k - 1], hs[k]))
         for j in range(k, 0, -1):
-            om = model["omega"][j - 1]
-            delta = om * np.cos(om * zs[j - 1]) * g
+            delta = activation_slope(model, j, zs[j - 1]) * g
             g = delta @ model["W_"][j - 1]
             if j > 1:
                 g = g + _tail_grad(model["tails"][j - 2], hs[j - 1])

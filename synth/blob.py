@@ -13,15 +13,17 @@ Layout (little-endian, version 1):
     28      4     f32 omega_hidden  (frequency of hidden layers 2..L)
     32      16    u8 tail kind per layer i = 1..L (0 = linear, 1 = multiplicative),
                   unused entries 0
-    48      16    reserved, zero
+    48      1     u8 activation: 0 = SIREN sine sin(omega z),
+                  1 = FINER variable-periodic sine sin(omega (|z| + 1) z)
+    49      15    reserved, zero
     64      ...   f32 parameters, in this order:
                   W_1 [W x 3] row-major, b_1 [W],
                   for j = 2..L: W_j [W x W] row-major (out x in), b_j [W],
                   for i = 1..L: linear tail:          a [W], c
                                 multiplicative tail:  a0 [W], c0, a1 [W], c1
 
-Hidden layer j computes h_j = sin(omega_j * (W_j h_{j-1} + b_j)) (the SIREN
-form); tail i is the linear head a.h + c or the product of two linear heads
+Hidden layer j computes h_j = sigma(omega_j, W_j h_{j-1} + b_j) with the
+activation named in the header (SIREN or FINER, the two backbones of Sec. 4.1); tail i is the linear head a.h + c or the product of two linear heads
 (a0.h + c0)(a1.h + c1) (Sec. 3.1, Eq. 2 and Eq. 3).
 """
 
@@ -35,6 +37,7 @@ HEADER_BYTES = 64
 MAX_LAYERS = 16
 TAIL_LINEAR = 0
 TAIL_MULT = 1
+ACTIVATIONS = {"sine": 0, "finer": 1}
 
 
 def blob_nbytes(L, W, tail_kinds):
@@ -51,7 +54,8 @@ def write_blob(model):
     ``model`` keys: ``omega_first``, ``omega_hidden`` (floats), ``weights``
     (list of L arrays: [W,3] then [W,W]), ``biases`` (list of L [W] arrays),
     ``tails`` (list of L dicts: ``{"kind": 0, "a", "c"}`` or
-    ``{"kind": 1, "a0", "c0", "a1", "c1"}``). Arrays are cast to float32.
+    ``{"kind": 1, "a0", "c0", "a1", "c1"}``), optionally ``activation``
+    (``"sine"``, the default, or ``"finer"``). Arrays are cast to float32.
     """
     weights = model["weights"]
     biases = model["biases"]
@@ -68,6 +72,7 @@ def write_blob(model):
                      float(model["omega_first"]), float(model["omega_hidden"]))
     for i, k in enumerate(kinds):
         head[32 + i] = k
+    head[48] = ACTIVATIONS[model.get("activation", "sine")]
     parts = [bytes(head)]
 
     def f32(a, shape):

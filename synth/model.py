@@ -6,6 +6,11 @@ publishes: first layer W_1 ~ U(-1/fan_in, 1/fan_in), hidden layers
 W_j ~ U(-sqrt(6/fan_in)/omega, sqrt(6/fan_in)/omega), biases
 ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), omega = 30.
 
+FINER backbone (``activation="finer"``, sin(omega (|z| + 1) z)): the same
+weight draws; FINER widens the range of the first layer's bias so that |z|,
+and with it the local frequency, varies across the input; here b_1 ~ U(-1, 1)
+(the bound is this generator's choice).
+
 Tail scales. A trained SAND model has a first tail that carries the signed
 distance and later tails that carry small residuals which shrink with depth
 (Sec. 4.3, Table 2). Random tails cannot reproduce training, so two synthetic
@@ -35,7 +40,8 @@ def residual_sigma(i):
     return 1.6e-2 * 0.5 ** (i - 2)
 
 
-def siren_tmlp(seed, L, W, omega=30.0, tails="mult", scale=TailScale.RESIDUAL):
+def siren_tmlp(seed, L, W, omega=30.0, tails="mult", scale=TailScale.RESIDUAL,
+               activation="sine"):
     """Draw a T-MLP parameter dict (the ``write_blob`` input).
 
     ``tails``: ``"linear"`` (every tail linear) or ``"mult"`` (tail 1 linear,
@@ -48,8 +54,11 @@ def siren_tmlp(seed, L, W, omega=30.0, tails="mult", scale=TailScale.RESIDUAL):
     scale = TailScale(scale)
     rng = np.random.Generator(np.random.PCG64(seed))
     weights, biases = [], []
+    if activation not in ("sine", "finer"):
+        raise ValueError("activation must be 'sine' or 'finer'")
+    b1 = 1.0 if activation == "finer" else 1.0 / np.sqrt(3.0)
     weights.append(rng.uniform(-1.0 / 3.0, 1.0 / 3.0, size=(W, 3)))
-    biases.append(rng.uniform(-1.0 / np.sqrt(3.0), 1.0 / np.sqrt(3.0), size=W))
+    biases.append(rng.uniform(-b1, b1, size=W))
     lim = np.sqrt(6.0 / W) / omega
     for _ in range(1, L):
         weights.append(rng.uniform(-lim, lim, size=(W, W)))
@@ -77,6 +86,7 @@ def siren_tmlp(seed, L, W, omega=30.0, tails="mult", scale=TailScale.RESIDUAL):
                               "a1": a1, "c1": c1})
     f32 = lambda a: np.asarray(a, dtype=np.float32)
     return {
+        "activation": activation,
         "omega_first": float(omega),
         "omega_hidden": float(omega),
         "weights": [f32(w) for w in weights],

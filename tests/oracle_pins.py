@@ -22,9 +22,9 @@ import oracle.tmlp as T
 import synth
 
 
-def tiny_model(seed, L, W, tails="mult", scale="plain"):
+def tiny_model(seed, L, W, tails="mult", scale="plain", activation="sine"):
     return oracle.parse_blob(synth.write_blob(
-        synth.siren_tmlp(seed, L, W, tails=tails, scale=scale)))
+        synth.siren_tmlp(seed, L, W, tails=tails, scale=scale, activation=activation)))
 
 
 # -- cell rule ---------------------------------------------------------------
@@ -139,11 +139,12 @@ def check_quadratic_form(seed=5, W=24, n=50):
 
 def truncated(model, k):
     return {"L": k, "W": model["W"], "omega": model["omega"][:k],
+            "activation": model["activation"],
             "W_": model["W_"][:k], "b_": model["b_"][:k], "tails": model["tails"][:k]}
 
 
-def check_truncation(seed=11, L=5, W=12, n=200):
-    model = tiny_model(seed, L, W)
+def check_truncation(seed=11, L=5, W=12, n=200, activation="sine"):
+    model = tiny_model(seed, L, W, activation=activation)
     rng = np.random.Generator(np.random.PCG64(seed))
     x = rng.uniform(-1, 1, size=(n, 3))
     d = rng.integers(1, L + 1, size=n)
@@ -176,8 +177,8 @@ def check_accumulation(seed=13, L=5, W=12, n=100):
         assert np.any(ys[k - 1] != 0.0)
 
 
-def check_scalar_twin(seed=17, L=3, W=8):
-    model = tiny_model(seed, L, W)
+def check_scalar_twin(seed=17, L=3, W=8, activation="sine"):
+    model = tiny_model(seed, L, W, activation=activation)
     x = synth.grid_points(8).astype(np.float64)
     d = (np.arange(x.shape[0]) % L) + 1
     got = T.forward(model, x, d)
@@ -186,9 +187,9 @@ def check_scalar_twin(seed=17, L=3, W=8):
     assert np.allclose(got, want, rtol=0, atol=1e-12), "scalar twin"
 
 
-def check_mpmath(seed=19, L=2, W=6, n=10):
+def check_mpmath(seed=19, L=2, W=6, n=10, activation="sine"):
     """Closed form at 50 digits: y_2 = sum of both tails of a 2-layer net."""
-    model = tiny_model(seed, L, W)
+    model = tiny_model(seed, L, W, activation=activation)
     rng = np.random.Generator(np.random.PCG64(seed))
     x = rng.uniform(-1, 1, size=(n, 3))
     got = T.forward(model, x, np.full(n, L))
@@ -199,8 +200,12 @@ def check_mpmath(seed=19, L=2, W=6, n=10):
         y = mp(0)
         for j in range(L):
             Wj, bj, om = model["W_"][j], model["b_"][j], mp(model["omega"][j])
-            h = [mpmath.sin(om * (mpmath.fsum(mp(float(Wj[u, k])) * h[k] for k in range(len(h)))
-                                  + mp(float(bj[u])))) for u in range(W)]
+            z = [mpmath.fsum(mp(float(Wj[u, k])) * h[k] for k in range(len(h))) + mp(float(bj[u]))
+                 for u in range(W)]
+            if activation == "finer":
+                h = [mpmath.sin(om * (abs(v) + 1) * v) for v in z]
+            else:
+                h = [mpmath.sin(om * v) for v in z]
             t = model["tails"][j]
             dot = lambda v: mpmath.fsum(mp(float(v[k])) * h[k] for k in range(W))
             if t[0] == "linear":
@@ -241,11 +246,13 @@ def check_lod_and_far(seed=23, L=4, W=8, R=8):
 def torch_tmlp(model):
     Ws = [torch.from_numpy(w) for w in model["W_"]]
     bs = [torch.from_numpy(b) for b in model["b_"]]
+    finer = model["activation"] == "finer"
 
     def f(x, k):
         h, y = x, torch.zeros(x.shape[0], dtype=torch.float64)
         for j in range(k):
-            h = torch.sin(model["omega"][j] * (h @ Ws[j].T + bs[j]))
+            z = h @ Ws[j].T + bs[j]
+            h = torch.sin(model["omega"][j] * ((torch.abs(z) + 1) * z if finer else z))
             t = model["tails"][j]
             if t[0] == "linear":
                 y = y + h @ torch.from_numpy(t[1]) + t[2]
@@ -255,8 +262,8 @@ def torch_tmlp(model):
     return f
 
 
-def check_gradient_autograd(seed=29, L=4, W=16, n=120):
-    model = tiny_model(seed, L, W)
+def check_gradient_autograd(seed=29, L=4, W=16, n=120, activation="sine"):
+    model = tiny_model(seed, L, W, activation=activation)
     rng = np.random.Generator(np.random.PCG64(seed))
     x = rng.uniform(-1, 1, size=(n, 3))
     d = rng.integers(1, L + 1, size=n)
@@ -269,8 +276,8 @@ def check_gradient_autograd(seed=29, L=4, W=16, n=120):
         assert np.allclose(got[sel], xt.grad.numpy(), rtol=1e-10, atol=1e-10), f"grad depth {k}"
 
 
-def check_gradient_fd(seed=31, L=3, W=10, n=60, h=1e-6):
-    model = tiny_model(seed, L, W)
+def check_gradient_fd(seed=31, L=3, W=10, n=60, h=1e-6, activation="sine"):
+    model = tiny_model(seed, L, W, activation=activation)
     rng = np.random.Generator(np.random.PCG64(seed))
     x = rng.uniform(-1, 1, size=(n, 3))
     d = rng.integers(1, L + 1, size=n)
@@ -281,6 +288,50 @@ def check_gradient_fd(seed=31, L=3, W=10, n=60, h=1e-6):
         fd = (T.forward(model, x + e, d) - T.forward(model, x - e, d)) / (2 * h)
         scale = 1.0 + np.abs(got[:, a])
         assert np.all(np.abs(fd - got[:, a]) <= 1e-6 * scale), "central difference"
+
+
+# -- FINER activation (SAND-FINER backbone, Sec. 4.1) --------------------------
+
+def _finer_root(om, k):
+    """The positive z with om (z + 1) z = k pi / 2, solved at 50 digits."""
+    mpmath.mp.dps = 50
+    c = mpmath.mpf(k) * mpmath.pi / 2 / mpmath.mpf(om)
+    return float((mpmath.sqrt(1 + 4 * c) - 1) / 2)
+
+
+def check_finer_roots():
+    """sin(om (|z| + 1) z) is 0 where om (|z| + 1) z = m pi, (-1)^m where it
+    is (m + 1/2) pi, and odd in z: at the roots of the quadratic, not by
+    evaluating the formula."""
+    for om in (30.0, 7.5, 1.0):
+        m = {"L": 1, "omega": [om], "activation": "finer"}
+        for k in range(1, 81):
+            z = _finer_root(om, k)
+            v = T.activation(m, 1, np.array([z, -z, 0.0]))
+            assert v[2] == 0.0
+            assert v[1] == -v[0], "FINER activation must be odd"
+            if k % 2 == 0:
+                assert abs(v[0]) <= 2e-13, f"om={om}: zero at k={k}: {v[0]}"
+            else:
+                want = (-1.0) ** ((k - 1) // 2)
+                assert abs(v[0] - want) <= 1e-12, f"om={om}: extremum at k={k}: {v[0]}"
+
+
+def check_finer_slope():
+    """The activation's derivative against fourth-order central differences
+    of the activation itself (away from the kink of |z| at 0, where the
+    slope is om)."""
+    rng = np.random.Generator(np.random.PCG64(71))
+    z = np.concatenate([rng.uniform(-2, -0.01, 300), rng.uniform(0.01, 2, 300)])
+    for act in ("finer", "sine"):
+        for om in (30.0, 2.5):
+            m = {"L": 1, "omega": [om], "activation": act}
+            h = 1e-4
+            f = lambda v: T.activation(m, 1, v)
+            fd = (8 * (f(z + h) - f(z - h)) - (f(z + 2 * h) - f(z - 2 * h))) / (12 * h)
+            got = T.activation_slope(m, 1, z)
+            assert np.all(np.abs(fd - got) <= 1e-6 * (1 + np.abs(got))), f"{act} slope, om={om}"
+            assert abs(T.activation_slope(m, 1, np.array([0.0]))[0] - om) < 1e-12
 
 
 # -- network-depth map construction (Sec. 3.2, Eq. 5-7) ----------------------
@@ -606,4 +657,10 @@ ALL_CHECKS = [
     check_dynamic_vanishing_tails, check_dynamic_scalar_twin,
     check_octree_brute_force, check_octree_constant_models, check_octree_invariants,
     check_octree_lookup,
+    check_finer_roots, check_finer_slope,
+    lambda: check_scalar_twin(activation="finer"),
+    lambda: check_mpmath(activation="finer"),
+    lambda: check_truncation(activation="finer"),
+    lambda: check_gradient_autograd(activation="finer"),
+    lambda: check_gradient_fd(activation="finer"),
 ]

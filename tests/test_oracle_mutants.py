@@ -118,6 +118,27 @@ def _gradient_no_intermediate_tails(model, xyz, d):
 
 _ORIG_FORWARD = T.forward
 _ORIG_GRADIENT = T.gradient
+_ORIG_ACT = T.activation
+_ORIG_SLOPE = T.activation_slope
+
+
+def _finer_no_abs_term(model, j, z):
+    if model["activation"] == "finer":
+        return np.sin(model["omega"][j - 1] * z)            # |z| dropped: plain SIREN
+    return _ORIG_ACT(model, j, z)
+
+
+def _finer_signed(model, j, z):
+    if model["activation"] == "finer":
+        return np.sin(model["omega"][j - 1] * (z + 1.0) * z)  # abs dropped
+    return _ORIG_ACT(model, j, z)
+
+
+def _finer_slope_without_two(model, j, z):
+    if model["activation"] == "finer":
+        om = model["omega"][j - 1]
+        return om * (np.abs(z) + 1.0) * np.cos(om * (np.abs(z) + 1.0) * z)
+    return _ORIG_SLOPE(model, j, z)
 
 
 # -- depth-map construction mutants --------------------------------------------
@@ -293,6 +314,9 @@ MUTANTS = {
     "octree min-pooling near leaves": (OT, "build", _octree_variant(min_pool=True)),
     "octree subdivides past D": (OT, "build", _octree_variant(extra_level=True)),
     "octree lookup axes swapped": (OT, "lookup", _lookup_xz_swapped),
+    "finer activation drops |z|": ("activation", _finer_no_abs_term),
+    "finer activation without abs": ("activation", _finer_signed),
+    "finer slope without the factor 2": ("activation_slope", _finer_slope_without_two),
 }
 
 

@@ -110,3 +110,19 @@ def test_octree_invariants():
 
 def test_octree_lookup_lands_in_containing_leaf():
     P.check_octree_lookup()
+
+
+# FINER backbone (SAND-FINER, Sec. 4.1; the activation is FINER's own)
+
+def test_finer_zeros_extrema_and_odd_symmetry():
+    P.check_finer_roots()
+
+
+def test_activation_slopes_match_central_differences():
+    P.check_finer_slope()
+
+
+@pytest.mark.parametrize("check", ["scalar_twin", "mpmath", "truncation", "gradient_autograd",
+                                   "gradient_fd"])
+def test_finer_network(check):
+    getattr(P, "check_" + check)(activation="finer")
