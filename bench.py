@@ -29,7 +29,9 @@ L, W = 8, 256
 MODEL_SEED, SURFACE_SEED = 1000, 2000
 PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tmlp_bf16_512grid_traffic.json")
-KERNEL_SOURCES = ["paper_2604_25936_amd/csrc/tmlp.hip", "paper_2604_25936_amd/csrc/mfma_common.h",
+KERNEL_SOURCES = ["paper_2604_25936_amd/csrc/tmlp_kernels.h",
+                  "paper_2604_25936_amd/csrc/tmlp_sine.hip",
+                  "paper_2604_25936_amd/csrc/mfma_common.h",
                   "paper_2604_25936_amd/csrc/sand_internal.h"]
 
 
@@ -233,7 +235,7 @@ def gen_inputs(legs, n_models):
     workers = max(1, min(16, os.cpu_count() or 1))
     with concurrent.futures.ProcessPoolExecutor(max_workers=workers) as ex:
         fut_c2 = ex.submit(synth.band_map_c2, synth.random_primitives(SURFACE_SEED), 128, L)
-        fut_c5 = ex.submit(_c5_points) if "grad" in legs else None
+        fut_c5 = ex.submit(_c5_points) if ("grad" in legs or "finer" in legs) else None
         fut_c4 = [ex.submit(_c4_inputs, k) for k in range(n_models)] if "serving" in legs else []
         out["c2_map"] = fut_c2.result()
         if fut_c5 is not None:
@@ -423,6 +425,69 @@ def grad_leg(sand, torch, inputs, dm_model):
     return out
 
 
+def error_sample(n, n_err=1 << 20):
+    """The seeded 1M-point uniform subsample of the 512^3 grid (without
+    replacement) on which SDF errors are measured: indices and points."""
+    import synth
+    idx = synth.sample_indices(n, n_err, seed=11)
+    return idx, synth.grid_points_at(G, idx)
+
+
+def error_study(sand, torch, model, dm, blob, dmap, xyz, sample, precs, sdf):
+    """Max and mean |SDF - FP64 oracle| of adaptive queries over the whole
+    512^3 grid, read at the sample's points, and sign agreement among sample
+    points with |y_oracle| < 0.01."""
+    import numpy as np
+    import oracle
+    idx, xs = sample
+    ref = oracle.parse_blob(blob)
+    want = oracle.forward(ref, xs, oracle.lookup_depth(xs, dmap, L))
+    near = np.abs(want) < 0.01
+    idx_t = torch.from_numpy(idx).to(xyz.device)
+    out = {"sample_points": int(len(idx)), "sample_points_near_surface": int(near.sum())}
+    for prec in precs:
+        sand.query(model, dm, xyz, out=sdf, precision=prec)
+        got = sdf[idx_t].cpu().numpy().astype(np.float64)
+        err = np.abs(got - want)
+        out[prec] = {"max_abs_err": float(err.max()), "mean_abs_err": float(err.mean()),
+                     "sign_agreement_near_surface": float(np.mean(
+                         np.sign(got[near]) == np.sign(want[near]))) if near.any() else None}
+    return out
+
+
+def finer_leg(sand, torch, inputs, xyz, dmap, sample, ws):
+    """SAND-FINER (Sec. 4.1): the 8x256 model on the FINER backbone,
+    sin(omega (|z| + 1) z), same map and grid. Throughput per precision and
+    mode, the T-MLP kernel's algorithmic MFMA rate, the 1M-sample error
+    study, and forward + gradient over the 1920x1080 camera-ray samples."""
+    import numpy as np
+    import oracle
+    import synth
+    blob = synth.write_blob(synth.siren_tmlp(MODEL_SEED, L, W, tails="mult", scale="residual",
+                                             activation="finer"))
+    model = sand.load_model(blob, 0)
+    dm = sand.build_depthmap(model, dmap)
+    n = xyz.shape[0]
+    sdf = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    depth = torch.empty(n, dtype=torch.uint8, device=xyz.device)
+    sand.query(model, dm, xyz, out=sdf, precision="bf16", depth_out=depth, workspace=ws)
+    hist = torch.bincount(depth.to(torch.int64), minlength=L + 1).cpu().numpy()
+    out = {"model": "8x256 FINER backbone (first-layer bias U(-1, 1)), same draws otherwise"}
+    for prec, mode in (("bf16", "adaptive"), ("fp16", "adaptive"), ("fp32", "adaptive"),
+                       ("bf16", "full"), ("fp32", "full")):
+        k = 2 if mode == "full" else 5
+        t = time_steps(lambda p=prec, m=mode: sand.query(model, dm, xyz, out=sdf, precision=p,
+                                                         mode=m, workspace=ws), k, 1)
+        _, ms = sand.query_timed(model, dm, xyz, out=sdf, precision=prec, mode=mode, workspace=ws)
+        fl = n * 2 * (L - 1) * W * W if mode == "full" else hidden_flops(hist, W)
+        out[f"{mode}_{prec}"] = {"queries_per_s": n / t, "ms_per_step": t * 1e3, "tmlp_ms": ms[3],
+                                 "mfma_frac": fl / (ms[3] / 1e3) / 1e12 / PEAK[prec]}
+    out["errors"] = error_study(sand, torch, model, dm, blob, dmap, xyz, sample,
+                                ("bf16", "fp16", "fp32"), sdf)
+    out["gradient"] = grad_leg(sand, torch, inputs, (model, dm, blob, dmap))
+    return out
+
+
 def c3_leg(sand, torch, xyz, dmap, n_err=1 << 20):
     """8x336 on the 512^3 grid: throughput per precision and the error study
     (max/mean |SDF error| vs the FP64 oracle on a seeded 1M-point sample, and
@@ -467,7 +532,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--legs", default="all",
                     help="'all', or a comma list of headline,compare,c3,grad,serving,mapbuild,"
-                         "octree,cpu")
+                         "octree,cpu,errors,finer")
     ap.add_argument("--cpu-sample", type=int, default=131072)
     ap.add_argument("--serving-models", type=int, default=64)
     ap.add_argument("--headline-mode", default="adaptive", choices=["adaptive", "full"],
@@ -480,7 +545,8 @@ def main():
               "shards by splitting the point set, with no exchange, and is not run on several "
               "GPUs here.", file=sys.stderr)
         sys.exit(2)
-    legs = {"headline", "compare", "c3", "grad", "serving", "mapbuild", "octree", "cpu"} \
+    legs = {"headline", "compare", "c3", "grad", "serving", "mapbuild", "octree", "cpu",
+            "errors", "finer"} \
         if args.legs == "all" else \
         set(args.legs.split(",")) | {"headline"}
 
@@ -614,6 +680,24 @@ def main():
             log(f"{name} leg failed: {e!r}")
             line[name] = {"error": repr(e)}
 
+    sample = error_sample(n) if ("errors" in legs or "finer" in legs) else None
+    if "errors" in legs:
+        log("error study: the headline model, and the same model with unit-scale tails (stress)")
+
+        def errors():
+            out = {"headline": error_study(sand, torch, model, dm, blob, dmap, xyz, sample,
+                                           ("bf16", "fp16", "fp32"), sdf)}
+            sblob = synth.write_blob(synth.siren_tmlp(MODEL_SEED, L, W, tails="mult",
+                                                      scale="plain"))
+            sm = sand.load_model(sblob, 0)
+            out["unit_scale_tails"] = error_study(sand, torch, sm, sand.build_depthmap(sm, dmap),
+                                                  sblob, dmap, xyz, sample,
+                                                  ("bf16", "fp16", "fp32"), sdf)
+            return out
+        secondary("errors_1m_sample", errors)
+    if "finer" in legs:
+        log("FINER leg: the 8x256 model on the FINER backbone")
+        secondary("finer", lambda: finer_leg(sand, torch, inputs, xyz, dmap, sample, ws))
     if "c3" in legs:
         log("8x336 leg: throughput per precision and error study")
         secondary("width336", lambda: c3_leg(sand, torch, xyz, dmap))

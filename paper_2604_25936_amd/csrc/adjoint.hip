@@ -1,478 +1,10 @@
-// Input gradient of the T-MLP output by reverse accumulation (gfx950).
-//
-// For a point with exit depth d the output is y_d = t_1 + ... + t_d (Eq. 2),
-// t_j the tail of layer j (linear, or the product form of Eq. 3), and
-// h_j = sin(omega_j z_j), z_j = W_j h_{j-1} + b_j. With g_j = dy/dh_j and
-// delta_j = cos(omega_j z_j) * g_j:
-//     g_d     = dt_d/dh_d,
-//     g_{j-1} = (omega_j W_j)^T delta_j + dt_{j-1}/dh_{j-1},
-//     dy/dx   = (omega_1 W_1)^T delta_1,
-// with dt/dh = u1 a0 + u0 a1 for a tail (a0.h + c0)(a1.h + c1), u0 and u1 its
-// two factors (a linear tail is stored with a1 = 0, c1 = 1).
-//
-// One workgroup handles a tile of points of equal depth, as the forward
-// kernel does:
-//  * forward recompute: the same MFMA chain, and each block's epilogue also
-//    writes cos(omega z) of its units to a per-workgroup global stash (in
-//    the lanes' own accumulator layout, 16-bit for BF16/FP16, FP32 for
-//    FP32) and each layer's tail factors u0, u1 to LDS;
-//  * backward: g_{j-1} is one MFMA product per output block with the
-//    transposed weights (packed with the same permuted K order, so the
-//    packed delta_j registers are the B operand as they stand); the
-//    epilogue adds the tail term, multiplies by the stashed cosine and packs
-//    delta_{j-1}; at layer 1 it accumulates dy/dx on the vector ALU instead.
+// Host-side entry points of the input-gradient kernel: dispatch on the
+// model's activation to the kernel built for it (adjoint_sine.hip,
+// adjoint_finer.hip), and the stash and tile geometry.
 
 #include "mfma_common.h"
 
 namespace sand {
-
-namespace {
-
-using namespace mfma;
-
-// Bytes of stashed cosines per lane per output block.
-template <int PREC>
-constexpr int stash_lane_bytes() {
-  return PREC == PREC_FP32 ? 16 : 32;
-}
-
-template <int PREC>
-__device__ __forceinline__ void stash_put(char* p, const float (&c)[Tr<PREC>::NR]) {
-  if constexpr (PREC == PREC_FP32) {
-    *(f32x4*)p = f32x4{c[0], c[1], c[2], c[3]};
-  } else {
-    using V = typename Tr<PREC>::V;
-    V lo, hi;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      lo[k] = (typename Tr<PREC>::E)c[k];
-      hi[k] = (typename Tr<PREC>::E)c[8 + k];
-    }
-    *(V*)p = lo;
-    *(V*)(p + 16) = hi;
-  }
-}
-
-template <int PREC>
-__device__ __forceinline__ void stash_get(const char* p, float (&c)[Tr<PREC>::NR]) {
-  if constexpr (PREC == PREC_FP32) {
-    const f32x4 v = *(const f32x4*)p;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) c[k] = v[k];
-  } else {
-    using V = typename Tr<PREC>::V;
-    const V lo = *(const V*)p, hi = *(const V*)(p + 16);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      c[k] = (float)lo[k];
-      c[8 + k] = (float)hi[k];
-    }
-  }
-}
-
-template <int PREC, int KS>
-__device__ __forceinline__ void pin_out(const typename Tr<PREC>::V (&out)[KS], int rb) {
-  using T = Tr<PREC>;
-  if constexpr (T::VB == 16) {
-    asm volatile("" ::"v"(out[2 * rb]), "v"(out[2 * rb + 1]));
-  } else {
-#pragma unroll
-    for (int e = 0; e < T::NR; ++e) asm volatile("" ::"v"(out[4 * rb + e]));
-  }
-}
-
-// What a forward epilogue keeps of cos of the sine argument: FE_STASH
-// writes it to the stash (and the packed activations to out); FE_NONE keeps
-// nothing (layer 1 of a deeper tile: the backward recomputes it); FE_REGS
-// packs the cosines into out instead of the activations (the tile's last
-// layer, whose activations feed nothing and whose cosines the backward
-// needs first).
-enum FwdKeep { FE_STASH, FE_NONE, FE_REGS };
-
-// Forward epilogue: sine, tail partial sums, and the cosines as FwdKeep says.
-template <int PREC, int KS, int KEEP>
-__device__ __forceinline__ void fwd_epilogue(const char* tails, int g, int rb,
-                                             const typename Tr<PREC>::Acc& acc,
-                                             typename Tr<PREC>::V (&out)[KS], float& s0,
-                                             float& s1, char* stash) {
-  using T = Tr<PREC>;
-  float h[T::NR], cs[T::NR];
-#pragma unroll
-  for (int i = 0; i < T::NR / 4; ++i) {
-    const f32x4 ta = T::tail_vec(tails, 0, i, g);
-    const f32x4 tb = T::tail_vec(tails, 1, i, g);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = 4 * i + k;
-      h[e] = __builtin_amdgcn_sinf(acc[e]);
-      if constexpr (KEEP != FE_NONE) cs[e] = __builtin_amdgcn_cosf(acc[e]);
-      s0 = fmaf(ta[k], h[e], s0);
-      s1 = fmaf(tb[k], h[e], s1);
-    }
-  }
-  if constexpr (KEEP == FE_REGS) {
-    T::template store<KS>(out, rb, cs);
-  } else {
-    T::template store<KS>(out, rb, h);
-    if constexpr (KEEP == FE_STASH) stash_put<PREC>(stash, cs);
-  }
-  asm volatile("" ::"v"(s0), "v"(s1));
-  pin_out<PREC, KS>(out, rb);
-}
-
-// The NR cosines of output block rb that fwd_epilogue<FE_REGS> packed into
-// act, as FP32 (the same 16-bit rounding as the stash).
-template <int PREC, int KS>
-__device__ __forceinline__ void cos_from_regs(const typename Tr<PREC>::V (&act)[KS], int rb,
-                                              float (&cs)[Tr<PREC>::NR]) {
-  using T = Tr<PREC>;
-  if constexpr (T::VB == 16) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      cs[k] = (float)act[2 * rb][k];
-      cs[8 + k] = (float)act[2 * rb + 1][k];
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < T::NR; ++e) cs[e] = act[4 * rb + e];
-  }
-}
-
-// Backward epilogue of one block: delta' = cos * (acc + u1 a0 + u0 a1).
-// Packs it for the next backward product, or (at layer 1) accumulates the
-// input gradient with the (omega_1 W_1) rows from w1t.
-template <int PREC, int KS>
-__device__ __forceinline__ void bwd_epilogue(const float* tails, int tstride, int g, int rb,
-                                             const typename Tr<PREC>::Acc& acc, float u0,
-                                             float u1, const float (&cs)[Tr<PREC>::NR],
-                                             typename Tr<PREC>::V (&out)[KS], bool last,
-                                             const char* w1t, float (&gx)[3]) {
-  using T = Tr<PREC>;
-  float dl[T::NR];
-#pragma unroll
-  for (int i = 0; i < T::NR / 4; ++i) {
-    const int row = T::tail_row(i, g);
-    const f32x4 ta = *(const f32x4*)(tails + row);
-    const f32x4 tb = *(const f32x4*)(tails + tstride + row);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = 4 * i + k;
-      dl[e] = cs[e] * fmaf(u1, ta[k], fmaf(u0, tb[k], acc[e]));
-    }
-  }
-  if (last) {
-#pragma unroll
-    for (int i = 0; i < T::NR / 4; ++i) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = 4 * i + k;
-        const int u = T::BM * rb + T::tail_row(i, g) + k;
-        const f32x4 w = *(const f32x4*)(w1t + u * 16);
-        gx[0] = fmaf(dl[e], w[0], gx[0]);
-        gx[1] = fmaf(dl[e], w[1], gx[1]);
-        gx[2] = fmaf(dl[e], w[2], gx[2]);
-      }
-    }
-    asm volatile("" ::"v"(gx[0]), "v"(gx[1]), "v"(gx[2]));
-  } else {
-    T::template store<KS>(out, rb, dl);
-    pin_out<PREC, KS>(out, rb);
-  }
-}
-
-template <int PREC, int WP>
-struct AdjCfg {
-  using C = Cfg<PREC, WP>;
-  static constexpr int SLOT = C::CH > C::CH_B ? C::CH : C::CH_B;
-  static constexpr int W1T = WP * 16;
-  static constexpr int UST = C::NW * kMaxLayers * Tr<PREC>::NQ * 2 * 4;   // tail factors
-  static constexpr int LDS = 2 * SLOT + C::L1B + W1T + UST;
-  // stash bytes per wavefront and layer
-  static constexpr int STASH_WL = C::RB * 64 * stash_lane_bytes<PREC>();
-};
-
-// Per-wavefront view of the stash: cosines of (layer j, block rb).
-template <int PREC, int WP>
-__device__ __forceinline__ char* stash_at(char* base, int j, int rb) {
-  return base + ((size_t)(j - 1) * Cfg<PREC, WP>::RB + rb) * 64 * stash_lane_bytes<PREC>();
-}
-
-// One forward hidden layer j: in -> out, cosines stashed, or (last: the
-// tile's exit layer) packed into out; returns the tail partial sums.
-template <int PREC, int WP>
-__device__ __forceinline__ void adj_fwd_layer(const char* __restrict__ hidden, char* ring, int wave,
-                                              int lane, int g, int& c, int nc, int j, bool last,
-                                              const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
-                                              typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
-                                              char* stash, float& s0, float& s1) {
-  using C = Cfg<PREC, WP>;
-  using A = AdjCfg<PREC, WP>;
-  using T = Tr<PREC>;
-  using V = typename T::V;
-  s0 = s1 = 0.0f;
-  const V bb = T::bias_b(g);
-#pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb) {
-    const bool pre = c + 1 < nc;
-    if (pre)
-      load_chunk<C::CH, C::NW>(hidden + (size_t)(c + 1) * C::CH, ring + ((c + 1) & 1) * A::SLOT,
-                               wave, lane);
-    const char* slot = ring + (c & 1) * A::SLOT;
-    // bias step first, then the K steps: the forward kernel's order, so the
-    // recomputed values are bit-identical to a plain query
-    typename T::Acc acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb,
-                                 typename T::Acc{});
-#pragma unroll
-    for (int s = 0; s < C::KS; ++s)
-      acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
-    if (last)
-      fwd_epilogue<PREC, C::KS, FE_REGS>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1, nullptr);
-    else
-      fwd_epilogue<PREC, C::KS, FE_STASH>(slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
-                                          stash_at<PREC, WP>(stash, j, rb));
-    if (pre) wait_chunk();
-    __syncthreads();
-    ++c;
-  }
-}
-
-// One backward layer j (j >= 2): in = delta'_j -> out = delta'_{j-1}, or the
-// input gradient when j == 2. Layer 1's cosines are recomputed from the
-// point (l1: the layer-1 chunks in LDS): its product is four inputs deep.
-template <int PREC, int WP>
-__device__ __forceinline__ void adj_bwd_layer(const char* __restrict__ bwd, char* ring, int wave,
-                                              int lane, int g, int& c, int nc, int d, int j,
-                                              const char* l1, float px, float py, float pz,
-                                              const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
-                                              typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
-                                              char* stash, float v0, float v1, const char* w1t,
-                                              float (&gx)[3]) {
-  using C = Cfg<PREC, WP>;
-  using A = AdjCfg<PREC, WP>;
-  using T = Tr<PREC>;
-  using V = typename T::V;
-#pragma unroll
-  for (int rb = 0; rb < C::RB; ++rb) {
-    const bool pre = c + 1 < nc;
-    if (pre) {
-      // chunks run layer d, d-1, ..., 2 and blocks 0..RB-1 within a layer
-      const int c1 = c + 1;
-      const int jn = d - c1 / C::RB, rn = c1 % C::RB;
-      load_chunk<C::CH_B, C::NW>(bwd + ((size_t)(jn - 2) * C::RB + rn) * C::CH_B,
-                                 ring + (c1 & 1) * A::SLOT, wave, lane);
-    }
-    const char* slot = ring + (c & 1) * A::SLOT;
-    typename T::Acc acc = {};
-#pragma unroll
-    for (int s = 0; s < C::KS; ++s)
-      acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
-    float cs[T::NR];
-    if (j == 2) {
-      typename T::Acc z = {};
-#pragma unroll
-      for (int st = 0; st < T::L1S; ++st)
-        z = T::mma1(T::l1_a(l1 + rb * C::L1C, st, lane), T::l1_b(st, g, px, py, pz), z);
-#pragma unroll
-      for (int e = 0; e < T::NR; ++e) cs[e] = __builtin_amdgcn_cosf(z[e]);
-    } else {
-      stash_get<PREC>(stash_at<PREC, WP>(stash, j - 1, rb), cs);
-    }
-    bwd_epilogue<PREC, C::KS>((const float*)(slot + C::TAIL_OFF_B), T::BM, g, rb, acc, v0, v1, cs,
-                              out, j == 2, w1t, gx);
-    if (pre) wait_chunk();
-    __syncthreads();
-    ++c;
-  }
-}
-
-template <int PREC, int WP>
-__global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) {
-  using C = Cfg<PREC, WP>;
-  using A = AdjCfg<PREC, WP>;
-  using T = Tr<PREC>;
-  using V = typename T::V;
-  constexpr int Q = C::Q;
-  constexpr int NQ = T::NQ;
-  __shared__ __attribute__((aligned(16))) char lds[A::LDS];
-  char* ring = lds;
-  char* l1 = lds + 2 * A::SLOT;
-  char* w1t = l1 + C::L1B;
-  float* ust = (float*)(w1t + A::W1T);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = T::grp(lane), col = T::col(lane);
-  const QueryArgs& q = a.q;
-
-  __shared__ Plan splan;   // the plan's bucket bounds, read per tile
-  for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)q.m.chunks)[i];
-  for (int i = tid; i < A::W1T / 16; i += C::NT) ((uint4*)w1t)[i] = ((const uint4*)a.w1t)[i];
-  if (q.plan)
-    for (int i = tid; i < (int)(sizeof(Plan) / 8); i += C::NT)
-      ((int64_t*)&splan)[i] = ((const int64_t*)q.plan)[i];
-  __syncthreads();
-  const char* hidden = q.m.chunks + C::L1B;
-  const int L = q.m.L;
-  const int64_t total = q.plan ? splan.total_tiles : (q.n + Q - 1) / Q;
-  char* stash = a.stash + (size_t)blockIdx.x * a.stash_wg + (size_t)wave * L * A::STASH_WL +
-                lane * stash_lane_bytes<PREC>();
-  float* uw = ust + wave * kMaxLayers * NQ * 2;   // [layer][point][2]
-
-  // Tiles (deepest first) are drawn one at a time from a counter, so a
-  // workgroup that drew deep tiles draws fewer and none ends a whole deep
-  // tile after the others (a static round robin gave some workgroups one
-  // depth-L tile more).
-  __shared__ uint32_t drawn;
-  for (;;) {
-    if (tid == 0) drawn = atomicAdd(a.next_tile, 1u);
-    __syncthreads();
-    const int64_t tile = drawn;
-    __syncthreads();
-    if (tile >= total) break;
-    int d;
-    int64_t start, cnt;
-    if (q.plan) {
-      d = 1;
-      for (int dd = L; dd >= 1; --dd)
-        if (tile < splan.tile_end[dd]) {
-          d = dd;
-          break;
-        }
-      const int64_t local = tile - splan.tile_end[d + 1];
-      start = splan.start[d] + local * Q;
-      cnt = splan.count[d] - local * Q;
-    } else {
-      d = q.full_depth;
-      start = tile * Q;
-      cnt = q.n - start;
-    }
-    if (cnt > Q) cnt = Q;
-
-    const int qi = wave * NQ + col;
-    const bool ok = qi < cnt;
-    int64_t gi = 0;
-    float px = 0.0f, py = 0.0f, pz = 0.0f, dy = 0.0f;
-    if (ok) {
-      gi = q.perm ? (int64_t)q.perm[start + qi] : start + qi;
-      const float* p = q.xyz + 3 * gi;
-      px = p[0];
-      py = p[1];
-      pz = p[2];
-      dy = a.dy ? a.dy[gi] : 1.0f;
-    }
-
-    // ---------------- forward recompute with stash ----------------
-    V actA[C::KS], actB[C::KS];
-    float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll
-    for (int rb = 0; rb < C::RB; ++rb) {
-      const char* ch = l1 + rb * C::L1C;
-      typename T::Acc acc = {};
-#pragma unroll
-      for (int st = 0; st < T::L1S; ++st)
-        acc = T::mma1(T::l1_a(ch, st, lane), T::l1_b(st, g, px, py, pz), acc);
-      if (d == 1)
-        fwd_epilogue<PREC, C::KS, FE_REGS>(ch + T::L1S * T::L1AB, g, rb, acc, actA, s0, s1,
-                                           nullptr);
-      else
-        fwd_epilogue<PREC, C::KS, FE_NONE>(ch + T::L1S * T::L1AB, g, rb, acc, actA, s0, s1,
-                                           nullptr);
-    }
-    float u0 = T::lane_sum(s0) + q.m.c0[0], u1 = T::lane_sum(s1) + q.m.c1[0];
-    float y = fmaf(u0, u1, 0.0f);
-    if (g == 0) {
-      uw[col * 2] = u0;
-      uw[col * 2 + 1] = u1;
-    }
-    const int nc = (d - 1) * C::RB;
-    int c = 0;
-    if (nc > 0) {
-      load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
-      wait_chunk();
-      __syncthreads();
-    }
-    for (int j = 2; j <= d; ++j) {
-      if (j & 1)
-        adj_fwd_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, j, j == d, actB, actA, stash,
-                                s0, s1);
-      else
-        adj_fwd_layer<PREC, WP>(hidden, ring, wave, lane, g, c, nc, j, j == d, actA, actB, stash,
-                                s0, s1);
-      u0 = T::lane_sum(s0) + q.m.c0[j - 1];
-      u1 = T::lane_sum(s1) + q.m.c1[j - 1];
-      y = fmaf(u0, u1, y);
-      if (g == 0) {
-        uw[((j - 1) * NQ + col) * 2] = u0;
-        uw[((j - 1) * NQ + col) * 2 + 1] = u1;
-      }
-    }
-    if (q.sdf && g == 0 && ok) q.sdf[gi] = y;
-
-    // ---------------- backward ----------------
-    // exit tail of layer d: delta'_d = cos_d * (u1 a0 + u0 a1), into actA;
-    // cos_d is in layer d's output registers (actA for odd d, actB for even)
-    float gx[3] = {0.0f, 0.0f, 0.0f};
-    {
-      const float* tl = a.tails + (size_t)(d - 1) * 2 * WP;
-      auto exit_tail = [&](const V (&cosv)[C::KS]) {
-#pragma unroll
-        for (int rb = 0; rb < C::RB; ++rb) {
-          const typename T::Acc zero = {};
-          float cs[T::NR];
-          cos_from_regs<PREC, C::KS>(cosv, rb, cs);
-          bwd_epilogue<PREC, C::KS>(tl + T::BM * rb, WP, g, rb, zero, u0, u1, cs, actA, d == 1,
-                                    w1t, gx);
-        }
-      };
-      if (d & 1)
-        exit_tail(actA);
-      else
-        exit_tail(actB);
-    }
-    const int ncb = (d - 1) * C::RB;
-    c = 0;
-    if (ncb > 0) {
-      load_chunk<C::CH_B, C::NW>(a.bwd + (size_t)(d - 2) * C::RB * C::CH_B, ring, wave, lane);
-      wait_chunk();
-      __syncthreads();
-    }
-    for (int j = d; j >= 2; j -= 2) {
-      adj_bwd_layer<PREC, WP>(a.bwd, ring, wave, lane, g, c, ncb, d, j, l1, px, py, pz, actA,
-                              actB, stash,
-                              uw[((j - 2) * NQ + col) * 2], uw[((j - 2) * NQ + col) * 2 + 1], w1t,
-                              gx);
-      if (j - 1 < 2) break;
-      adj_bwd_layer<PREC, WP>(a.bwd, ring, wave, lane, g, c, ncb, d, j - 1, l1, px, py, pz,
-                              actB, actA, stash,
-                              uw[((j - 3) * NQ + col) * 2], uw[((j - 3) * NQ + col) * 2 + 1], w1t,
-                              gx);
-    }
-    const float gxs = T::lane_sum(gx[0]), gys = T::lane_sum(gx[1]), gzs = T::lane_sum(gx[2]);
-    if (g == 0 && ok) {
-      float* o = a.grad + 3 * gi;
-      o[0] = dy * gxs;
-      o[1] = dy * gys;
-      o[2] = dy * gzs;
-    }
-  }
-}
-
-template <int PREC, int WP>
-hipError_t launch_adj_one(const AdjointArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_adjoint<PREC, WP>), dim3((unsigned)grid), dim3(Cfg<PREC, WP>::NT), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int PREC>
-hipError_t launch_adj_prec(const AdjointArgs& a, int grid, hipStream_t s) {
-  switch (a.q.m.WP) {
-    case 64: return launch_adj_one<PREC, 64>(a, grid, s);
-    case 128: return launch_adj_one<PREC, 128>(a, grid, s);
-    case 256: return launch_adj_one<PREC, 256>(a, grid, s);
-    case 352: return launch_adj_one<PREC, 352>(a, grid, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-}  // namespace
 
 size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L) {
   const int BM = prec == PREC_FP32 ? 16 : 32;
@@ -481,11 +13,13 @@ size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L) {
 }
 
 hipError_t launch_adjoint(int prec, const AdjointArgs& a, int grid, hipStream_t s) {
-  if (prec == PREC_FP32) return launch_adj_prec<PREC_FP32>(a, grid, s);
-  if (prec == PREC_BF16) return launch_adj_prec<PREC_BF16>(a, grid, s);
-  return launch_adj_prec<PREC_FP16>(a, grid, s);
+  if (a.q.m.act == ACT_SINE) return launch_adjoint_act<ACT_SINE>(prec, a, grid, s);
+  if (a.q.m.act == ACT_FINER) return launch_adjoint_act<ACT_FINER>(prec, a, grid, s);
+  return hipErrorInvalidValue;
 }
 
-int adjoint_tile_points(int prec) { return prec == PREC_FP32 ? Cfg<PREC_FP32, 64>::Q : Cfg<PREC_BF16, 64>::Q; }
+int adjoint_tile_points(int prec) {
+  return prec == PREC_FP32 ? mfma::Cfg<PREC_FP32, 64>::Q : mfma::Cfg<PREC_BF16, 64>::Q;
+}
 
 }  // namespace sand

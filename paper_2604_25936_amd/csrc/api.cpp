@@ -48,7 +48,11 @@ DeviceGuard::~DeviceGuard() {
 }  // namespace sand
 
 extern "C" const char* sand_status_str(sand_status s) {
-  switch (s) {
+  // a C caller may pass any int: read the value as one, not as the enum
+  int32_t v;
+  static_assert(sizeof(v) == sizeof(s), "sand_status is an int");
+  std::memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case SAND_OK: return "ok";
     case SAND_ERR_INVALID: return "invalid argument";
     case SAND_ERR_FORMAT: return "malformed model or map";
@@ -78,6 +82,7 @@ struct Blob {
   int L = 0, W = 0;
   float om[2] = {0, 0};
   uint8_t kind[kMaxLayers] = {};
+  int act = ACT_SINE;
   std::vector<const float*> Wm, b;      // per layer
   std::vector<const float*> a0, a1;     // per tail (a1 null for linear)
   std::vector<float> c0, c1;            // per tail (c1 = 1 for linear)
@@ -104,7 +109,9 @@ sand_status parse_blob(const void* data, size_t nbytes, Blob& B, std::vector<flo
     if ((uint32_t)i < L ? (k > 1) : (k != 0))
       return fail(SAND_ERR_FORMAT, "model blob: bad tail kind %u at layer %d", k, i + 1);
   }
-  for (int i = 48; i < 64; ++i)
+  if (p[48] > ACT_FINER)
+    return fail(SAND_ERR_FORMAT, "model blob: unknown activation %u (0 sine, 1 FINER)", p[48]);
+  for (int i = 49; i < 64; ++i)
     if (p[i] != 0) return fail(SAND_ERR_FORMAT, "model blob: reserved header bytes not zero");
   size_t nf = (size_t)W * 3 + W + (size_t)(L - 1) * ((size_t)W * W + W);
   for (uint32_t i = 0; i < L; ++i) nf += (size_t)(W + 1) * (p[32 + i] ? 2 : 1);
@@ -116,8 +123,11 @@ sand_status parse_blob(const void* data, size_t nbytes, Blob& B, std::vector<flo
   std::memcpy(&store[nf], p + 24, 8);          // the two omegas
   for (size_t i = 0; i < nf + 2; ++i)
     if (!std::isfinite(store[i])) return fail(SAND_ERR_FORMAT, "model blob: non-finite value");
+  if (p[48] == ACT_FINER && (store[nf] == 0.0f || store[nf + 1] == 0.0f))
+    return fail(SAND_ERR_FORMAT, "model blob: a FINER model needs nonzero omegas");
   B.L = (int)L;
   B.W = (int)W;
+  B.act = p[48];
   B.om[0] = store[nf];
   B.om[1] = store[nf + 1];
   const float* q = store.data();
@@ -435,6 +445,7 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
   m->L = B.L;
   m->W = B.W;
   m->WP = WP;
+  m->act = B.act;
   m->num_cu = num_cu;
   m->dev = dev;
   m->bytes = total;
@@ -448,6 +459,9 @@ extern "C" sand_status sand_load_model(const void* blob, size_t nbytes, int devi
     a.L = B.L;
     a.WP = WP;
     a.chunk_bytes = Geo(p, WP).CH;
+    a.act = B.act;
+    a.kf[0] = (float)(kTwoPi / std::fabs((double)B.om[0]));
+    a.kf[1] = (float)(kTwoPi / std::fabs((double)B.om[1]));
     for (int i = 0; i < B.L; ++i) {
       a.c0[i] = B.c0[i];
       a.c1[i] = B.c1[i];

@@ -1,5 +1,5 @@
-// MFMA geometry and LDS streaming shared by the forward (tmlp.hip) and the
-// adjoint (adjoint.hip) T-MLP kernels on gfx950.
+// MFMA geometry, LDS streaming and the activations shared by the forward
+// (tmlp_kernels.h) and the adjoint (adjoint_kernels.h) T-MLP kernels on gfx950.
 #pragma once
 
 #include "sand_internal.h"
@@ -187,6 +187,29 @@ struct Tr<PREC_FP16> : Tr16<PREC_FP16> {
 };
 
 __device__ __forceinline__ float sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+
+// Argument, in revolutions, of a hidden unit's sine. The accumulator holds
+// u = omega z / (2 pi) (the packed weights carry omega / (2 pi)). SIREN's
+// sin(omega z) takes u itself; FINER's sin(omega (|z| + 1) z) takes
+// u (1 + |z|), with |z| = |u| kf and kf = 2 pi / omega.
+template <int ACT>
+__device__ __forceinline__ float act_arg(float u, float kf) {
+  if constexpr (ACT == ACT_FINER)
+    return u * fmaf(fabsf(u), kf, 1.0f);
+  else
+    return u;
+}
+
+// The activation's slope divided by omega, at accumulator value u with
+// argument arg = act_arg(u, kf): cos(omega z) for SIREN, and for FINER
+// (2|z| + 1) cos(omega (|z| + 1) z) (d/dz of (|z| + 1) z is 2|z| + 1).
+template <int ACT>
+__device__ __forceinline__ float act_slope(float u, float arg, float kf) {
+  if constexpr (ACT == ACT_FINER)
+    return __builtin_amdgcn_cosf(arg) * fmaf(fabsf(u), 2.0f * kf, 1.0f);
+  else
+    return __builtin_amdgcn_cosf(arg);
+}
 
 template <int PREC, int WP>
 struct Cfg {

@@ -11,6 +11,7 @@
 struct sand_model_s {
   int device = 0;
   int L = 0, W = 0, WP = 0;
+  int act = 0;                // sand::Act
   int num_cu = 0;
   char* dev = nullptr;        // one allocation holding the three packed precisions
   size_t bytes = 0;

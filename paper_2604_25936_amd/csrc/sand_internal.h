@@ -46,6 +46,11 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 enum Prec { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
 
+// Activation of the hidden layers (the model blob's header byte 48): the
+// SIREN sine sin(omega z) or the FINER variable-periodic sine
+// sin(omega (|z| + 1) z), z = W h + b (the two backbones of Sec. 4.1).
+enum Act { ACT_SINE = 0, ACT_FINER = 1 };
+
 // Padded widths the kernels are built for.
 inline int padded_width(int W) {
   if (W <= 64) return 64;
@@ -64,6 +69,9 @@ struct ModelArgs {
   float c0[kMaxLayers];    // tail bias of the first factor
   float c1[kMaxLayers];    // tail bias of the second factor (1 for linear)
   uint32_t lin_mask;       // bit j: tail j+1 is linear (second factor a1 = 0, c1 = 1)
+  int act;                 // Act
+  float kf[2];             // 2 pi / omega of layer 1 and of layers 2..L (FINER's |z| = |u| kf
+                           // for the omega / (2 pi)-scaled accumulator u)
 };
 
 // Sparse network-depth octree (Sec. 3.2), pointer-free. Node codes are
@@ -189,7 +197,14 @@ hipError_t launch_scatter(const uint8_t* depth, int64_t n, const int32_t* offs,
 hipError_t launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_bucketing_batch(BatchReq* reqs, int nreq, int64_t nblk, int max_depth,
                                   int tile_q, int64_t* total_tiles, hipStream_t s);
-hipError_t launch_tmlp_batch(int prec, int WP, const BatchArgs& a, int num_cu, hipStream_t s);
+hipError_t launch_tmlp_batch(int prec, int WP, int act, const BatchArgs& a, int num_cu,
+                             hipStream_t s);
+// The forward kernels of one activation (tmlp_sine.hip, tmlp_finer.hip):
+// what = 0 a query (q), 1 the resumed launch of compacted dynamic exit (q),
+// 2 a batch (b).
+template <int ACT>
+hipError_t launch_tmlp_act(int what, int prec, int WP, const QueryArgs* q, const BatchArgs* b,
+                           int num_cu, hipStream_t s);
 
 // network-depth map construction (mapbuild.hip)
 hipError_t launch_map_list(const uint8_t* near, int64_t cells, int32_t* list, uint32_t* count,
@@ -223,6 +238,9 @@ int tmlp_tile_points(int prec, int WP);   // forward tile (the plan's tile_q for
 int adjoint_tile_points(int prec);   // adjoint tile (the plan's tile_q for sand_query_grad)
 size_t adjoint_stash_bytes_per_wg(int prec, int WP, int L);
 hipError_t launch_adjoint(int prec, const AdjointArgs& a, int grid, hipStream_t s);
+// The input-gradient kernel of one activation (adjoint_sine.hip, adjoint_finer.hip).
+template <int ACT>
+hipError_t launch_adjoint_act(int prec, const AdjointArgs& a, int grid, hipStream_t s);
 hipError_t launch_tmlp(int prec, const QueryArgs& a, int num_cu, hipStream_t s);
 // Second launch of compacted dynamic exit: the records of a.spill, from
 // layer a.spill.layer + 1 on (a.xyz unused; a.sdf/a.depth_out indexed as in

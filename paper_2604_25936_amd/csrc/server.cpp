@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "sand_host.h"
+#include "batching.h"
 
 using namespace sand;
 
@@ -56,48 +57,6 @@ struct ReqLayout {
   }
 };
 
-// First-fit allocator over offsets of one device allocation.
-class Arena {
- public:
-  void init(size_t size) {
-    free_.clear();
-    free_[0] = size;
-  }
-  bool alloc(size_t n, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second < n) continue;
-      *off = it->first;
-      const size_t rest = it->second - n, at = it->first + n;
-      free_.erase(it);
-      if (rest) free_[at] = rest;
-      used += n;
-      peak = std::max(peak, used);
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    used -= n;
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + n == next->first) {
-      n += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        prev->second += n;
-        return;
-      }
-    }
-    free_[off] = n;
-  }
-  size_t used = 0, peak = 0;
-
- private:
-  std::map<size_t, size_t> free_;   // offset -> size of each free range
-};
-
 struct Req {
   sand_model model = nullptr;
   sand_depthmap map = nullptr;
@@ -107,6 +66,7 @@ struct Req {
   size_t bytes = 0, off = 0;
   sand_req_stats st{};
   bool done = false;
+  bool waiting = false;   // a sand_server_wait is blocked on this request
   sand_status status = SAND_OK;
 };
 
@@ -137,28 +97,33 @@ struct sand_server_s {
   std::thread sched;
   uint64_t submitted = 0, completed = 0, batches = 0;
   int max_batch = 0;
+  // host callbacks enqueued and not yet finished (destroy waits for zero)
+  int callbacks = 0;
   void run();
   void launch(Slot* s);
 };
 
 namespace {
 
-void finish_batch(Slot* s, sand_status st) {
+// Complete a batch: release its requests' memory and wake waiters. The
+// notifications are sent while the lock is held, so once a thread that
+// takes the lock sees the callback count at zero no callback touches the
+// server again (sand_server_destroy relies on it).
+void finish_batch(Slot* s, sand_status st, bool callback) {
   sand_server srv = s->srv;
   const double t = now_s();
-  {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    for (Req* r : s->reqs) {
-      if (r->st.t_done == 0.0) r->st.t_done = t;
-      r->st.t_copied = t;
-      r->status = st;
-      r->done = true;
-      srv->arena.release(r->off, r->bytes);
-      ++srv->completed;
-    }
-    s->reqs.clear();
-    s->busy = false;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  for (Req* r : s->reqs) {
+    if (r->st.t_done == 0.0) r->st.t_done = t;
+    r->st.t_copied = t;
+    r->status = st;
+    r->done = true;
+    srv->arena.release(r->off, r->bytes);
+    ++srv->completed;
   }
+  s->reqs.clear();
+  s->busy = false;
+  if (callback) --srv->callbacks;
   srv->cv_done.notify_all();
   srv->cv_work.notify_all();
 }
@@ -168,9 +133,25 @@ void on_kernels_done(void* p) {
   const double t = now_s();
   std::lock_guard<std::mutex> lk(s->srv->mu);
   for (Req* r : s->reqs) r->st.t_done = t;
+  --s->srv->callbacks;
+  s->srv->cv_done.notify_all();
 }
 
-void on_copied(void* p) { finish_batch((Slot*)p, SAND_OK); }
+void on_copied(void* p) { finish_batch((Slot*)p, SAND_OK, true); }
+
+// Enqueue a host callback, counted until it has run.
+hipError_t add_callback(sand_server srv, hipStream_t stream, void (*fn)(void*), void* arg) {
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    ++srv->callbacks;
+  }
+  const hipError_t e = hipLaunchHostFunc(stream, fn, arg);
+  if (e != hipSuccess) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    --srv->callbacks;
+  }
+  return e;
+}
 
 }  // namespace
 
@@ -214,17 +195,17 @@ void sand_server_s::launch(Slot* s) {
                                s->stream);
   if (e == hipSuccess) {
     BatchArgs ba{s->desc_dev, nreq, s->total_dev};
-    e = launch_tmlp_batch(prec, WP, ba, num_cu, s->stream);
+    e = launch_tmlp_batch(prec, WP, s->reqs[0]->model->act, ba, num_cu, s->stream);
   }
-  if (e == hipSuccess) e = hipLaunchHostFunc(s->stream, on_kernels_done, s);
+  if (e == hipSuccess) e = add_callback(this, s->stream, on_kernels_done, s);
   for (int i = 0; i < nreq && e == hipSuccess; ++i)
     e = hipMemcpyAsync(s->reqs[i]->sdf_host, s->desc_host[i].sdf, 4 * (size_t)s->reqs[i]->n,
                        hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipLaunchHostFunc(s->stream, on_copied, s);
+  if (e == hipSuccess) e = add_callback(this, s->stream, on_copied, s);
   if (e != hipSuccess) {
     // what was enqueued may still run; wait for it before releasing memory
     (void)hipStreamSynchronize(s->stream);
-    finish_batch(s, SAND_ERR_DEVICE);
+    finish_batch(s, SAND_ERR_DEVICE, false);
   }
 }
 
@@ -232,14 +213,10 @@ void sand_server_s::run() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    while (!pending.empty()) {
-      Req* r = pending.front();
-      size_t off;
-      if (!arena.alloc(r->bytes, &off)) break;   // FIFO: nothing overtakes the head
-      r->off = off;
-      r->st.t_admit = now_s();
-      admitted.push_back(r);
-      pending.pop_front();
+    const size_t first_new = admitted.size();
+    if (admit_fifo(pending, admitted, arena) > 0) {
+      const double t = now_s();
+      for (size_t i = first_new; i < admitted.size(); ++i) admitted[i]->st.t_admit = t;
     }
     Slot* free_slot = nullptr;
     bool any_busy = false;
@@ -248,21 +225,11 @@ void sand_server_s::run() {
       any_busy |= s->busy;
     }
     if (!admitted.empty() && free_slot) {
-      // admitted requests of the head's padded width, in order, up to the
-      // point cap (the head always goes)
-      const int WP = admitted.front()->model->WP;
-      int64_t points = 0;
-      for (auto it = admitted.begin();
-           it != admitted.end() && (int)free_slot->reqs.size() < kMaxBatchRequests;) {
-        const bool fits = free_slot->reqs.empty() || points + (*it)->n <= kBatchPointCap;
-        if ((*it)->model->WP == WP && fits) {
-          points += (*it)->n;
-          free_slot->reqs.push_back(*it);
-          it = admitted.erase(it);
-        } else {
-          ++it;
-        }
-      }
+      // admitted requests of the head's padded width and activation, in
+      // order, up to the point cap (the head always goes)
+      free_slot->reqs = take_batch(admitted, kBatchPointCap, kMaxBatchRequests, [](const Req* r) {
+        return std::make_pair(r->model->WP, r->model->act);
+      });
       free_slot->busy = true;
       ++batches;
       max_batch = std::max(max_batch, (int)free_slot->reqs.size());
@@ -381,10 +348,15 @@ extern "C" sand_status sand_server_wait(sand_server srv, uint64_t ticket, double
   if (it == srv->tickets.end())
     return fail(SAND_ERR_INVALID, "sand_server_wait: unknown ticket %llu", (unsigned long long)ticket);
   Req* r = it->second;
+  if (r->waiting)
+    return fail(SAND_ERR_INVALID, "sand_server_wait: ticket %llu already has a waiter",
+                (unsigned long long)ticket);
   auto ready = [r] { return r->done; };
+  r->waiting = true;
   if (timeout_s < 0) {
     srv->cv_done.wait(lk, ready);
   } else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+    r->waiting = false;
     return fail(SAND_ERR_TIMEOUT, "sand_server_wait: ticket %llu not done after %.3f s",
                 (unsigned long long)ticket, timeout_s);
   }
@@ -421,6 +393,11 @@ extern "C" void sand_server_destroy(sand_server srv) {
   }
   srv->cv_work.notify_all();
   if (srv->sched.joinable()) srv->sched.join();
+  {
+    // every batch is complete and no host callback still reads the server
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [srv] { return srv->callbacks == 0; });
+  }
   DeviceGuard guard(srv->device);
   for (Slot* s : srv->slots) {
     (void)hipStreamSynchronize(s->stream);

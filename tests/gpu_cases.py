@@ -58,3 +58,11 @@ def edge_points(R, n_random=2000, seed=3):
     nan = np.array([[np.nan, 0.1, 0.2], [0.3, np.nan, -0.4], [0.5, 0.5, np.nan],
                     [np.nan, np.nan, np.nan]], dtype=np.float32)
     return np.concatenate([pts, nan])
+
+
+@functools.lru_cache(maxsize=None)
+def finer_blob(W=256, seed=1000, L=8, tails="mult", scale="residual"):
+    """The 8x256 case on the FINER backbone (SAND-FINER): the same draws
+    except the first layer's wider bias range."""
+    return synth.write_blob(synth.siren_tmlp(seed, L, W, tails=tails, scale=scale,
+                                             activation="finer"))

@@ -58,6 +58,7 @@ def test_blob_format_errors():
         "tailkind": (lambda b: b.__setitem__(33, 7), sand.ERR_FORMAT),
         "unused_tail": (lambda b: b.__setitem__(40, 1), sand.ERR_FORMAT),
         "reserved": (lambda b: b.__setitem__(50, 1), sand.ERR_FORMAT),
+        "activation": (lambda b: b.__setitem__(48, 2), sand.ERR_FORMAT),
         "nan": (lambda b: struct.pack_into("<f", b, 64 + 8, float("nan")), sand.ERR_FORMAT),
         "inf_omega": (lambda b: struct.pack_into("<f", b, 24, float("inf")), sand.ERR_FORMAT),
     }
@@ -77,6 +78,29 @@ def test_blob_format_errors():
     st, _ = _load(wide)
     assert st == sand.ERR_UNSUPPORTED
     assert b"width" in sand.library().sand_last_error()
+
+
+def test_finer_blob_flag():
+    """Header byte 48 selects the activation: 1 (FINER) passes the format
+    checks (on a machine without a GPU the load then fails on the device,
+    not on the format); a FINER model with a zero omega is rejected, since
+    its argument omega (|z| + 1) z needs |z| recovered from omega z."""
+    fb = bytearray(synth.write_blob(synth.siren_tmlp(1, 2, 16, activation="finer")))
+    assert fb[48] == 1
+    st, h = _load(fb)
+    assert st != sand.ERR_FORMAT, sand.library().sand_last_error()
+    if st == sand.OK:
+        sand.library().sand_free_model(h)
+    z = bytearray(fb)
+    struct.pack_into("<f", z, 28, 0.0)
+    st, h = _load(z)
+    assert st == sand.ERR_FORMAT and b"omega" in sand.library().sand_last_error()
+    s = bytearray(synth.write_blob(synth.siren_tmlp(1, 2, 16)))
+    struct.pack_into("<f", s, 28, 0.0)
+    st, h = _load(s)
+    assert st != sand.ERR_FORMAT
+    if st == sand.OK:
+        sand.library().sand_free_model(h)
 
 
 def test_null_arguments():
