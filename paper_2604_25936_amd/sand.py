@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libsand.so")
+# SAND_LIBRARY names another build of the same library (the sanitizer build
+# of the host code that the CPU tests load)
+LIB_PATH = os.environ.get("SAND_LIBRARY") or os.path.join(_HERE, "_lib", "libsand.so")
 
 OK, ERR_INVALID, ERR_FORMAT, ERR_NOMEM, ERR_DEVICE, ERR_BUDGET, ERR_UNSUPPORTED, ERR_TIMEOUT = range(8)
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
