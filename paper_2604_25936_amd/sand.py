@@ -362,7 +362,9 @@ class Server:
         try:
             _check(library().sand_server_wait(self._h, ticket, float(timeout), ctypes.byref(st)))
         except SandError as e:
-            if e.status != ERR_TIMEOUT:
+            # a timeout leaves the request running, and an invalid ticket is
+            # unknown or has another waiter: its buffers stay referenced
+            if e.status not in (ERR_TIMEOUT, ERR_INVALID):
                 self._keep.pop(ticket, None)
             raise
         self._keep.pop(ticket, None)

@@ -228,9 +228,12 @@ def test_finer_server_mix(c2f):
     for (m, mdm, x, y, _) in reqs:
         want = sand.query(m, mdm, torch.from_numpy(x).to(DEV), precision="bf16").cpu().numpy()
         assert np.array_equal(y, want), f"request of {len(x)} points differs from alone"
-    x, y = reqs[3][2], reqs[3][3]
-    d = oracle.lookup_depth(x, dmap, 8)
-    assert_close(y.astype(np.float64), oracle.forward(ref, x, d), TOL["bf16"], "served FINER")
+    # request 2 went to the FINER model, request 3 to the SIREN one
+    for i, r_ in ((2, ref), (3, oracle.parse_blob(sblob))):
+        x, y = reqs[i][2], reqs[i][3]
+        d = oracle.lookup_depth(x, dmap, 8)
+        assert_close(y.astype(np.float64), oracle.forward(r_, x, d), TOL["bf16"],
+                     f"served request {i} ({r_['activation']})")
     srv.close()
 
 
@@ -252,7 +255,10 @@ def test_finer_octree_small():
     check_counts(tree, info, ny, 1e-5)
     x = np.random.Generator(np.random.PCG64(3)).uniform(-1, 1, size=(20000, 3)).astype(np.float32)
     y, d = run(model, dm, x, precision="fp32")
-    compare(ref, tree, x.astype(np.float64), y, d, s, r, "fp32", 1e-5, "FINER tree", ny=ny)
+    # far leaves hold y_L(centre) from the FP32 build, whose FINER error (up to
+    # ~7e-6 on this model) is the FP32 path's: their bound is the FP32 one
+    compare(ref, tree, x.astype(np.float64), y, d, s, r, "fp32", 1e-5, "FINER tree", ny=ny,
+            far_tol=TOL["fp32"])
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp32"])

@@ -107,7 +107,8 @@ def check_counts(tree, info, ny, eps):
         prev = di
 
 
-def compare(ref, tree, x, y, d, s, r, prec, eps, what, max_diff=0.0, ny=None, tol=None):
+def compare(ref, tree, x, y, d, s, r, prec, eps, what, max_diff=0.0, ny=None, tol=None,
+            far_tol=None):
     de, ve, lv = OT.lookup(tree, x)
     amb = ambiguous(ref, tree, x, lv, s, r, eps, ny)
     far = de == 0
@@ -116,7 +117,9 @@ def compare(ref, tree, x, y, d, s, r, prec, eps, what, max_diff=0.0, ny=None, to
         yo[~far] = oracle.forward(ref, x[~far], de[~far])
     bad_d = d != de
     err = np.abs(y - yo)
-    tol = np.where(far, 2e-6 * (1 + np.abs(yo)), TOL[prec] if tol is None else tol)
+    # a far leaf stores y_L at its centre from the build's FP32 evaluation
+    ftol = 2e-6 * (1 + np.abs(yo)) if far_tol is None else far_tol
+    tol = np.where(far, ftol, TOL[prec] if tol is None else tol)
     bad_v = (err > tol) & ~bad_d
     say(f"  {what}: n={len(x)}, far {int(far.sum())}, near {int((~far).sum())}, "
         f"leaf levels {np.bincount(lv, minlength=tree['D'] + 1).tolist()}, "

@@ -150,3 +150,85 @@ def test_zero_size_timeout_and_errors(models):
     srv.submit(models[1][1], models[1][3], x2, y2)
     srv.close()
     assert not np.any(np.isnan(y2)), "close() finishes queued requests"
+
+
+def _c4_model(k):
+    """Serving model k of the benchmark mix: 8x256 residual model (seed
+    1000 + k), its 128^3 band map (surface seed 2000 + k) and a pool of
+    near-surface points (generators only)."""
+    prims = synth.random_primitives(2000 + k)
+    return (c2_blob(256, seed=1000 + k), synth.band_map_c2(prims, R=128, L=8),
+            synth.near_surface_points(prims, 1 << 14, seed=5000 + k))
+
+
+def test_mix_equals_alone_16_models():
+    """16 of the benchmark's resident models, requests of log-uniform size in
+    [1e3, 4e6] (half a contiguous run of the 512^3 grid, half near-surface
+    points), all submitted at once under the benchmark's 4 GB budget: every
+    result equals the same query alone, bit for bit; the two smallest are
+    checked against the oracle."""
+    import concurrent.futures
+    n_models, n_req = 16, 40
+    with concurrent.futures.ProcessPoolExecutor(max_workers=8) as ex:
+        inputs = list(ex.map(_c4_model, range(n_models)))
+    ms = []
+    for blob, dmap, _ in inputs:
+        m = sand.load_model(blob, 0)
+        ms.append((m, sand.build_depthmap(m, dmap)))
+    rng = np.random.Generator(np.random.PCG64(77))
+    sizes = np.exp(rng.uniform(np.log(1e3), np.log(4e6), size=n_req)).astype(np.int64)
+    say(f"case: {n_req} requests over {n_models} models, {int(sizes.sum())} points, bf16")
+    srv = sand.Server(0, budget_bytes=4 << 30, precision="bf16", n_streams=3)
+    reqs = []
+    for i, n in enumerate(sizes):
+        k = i % n_models
+        half = int(n) // 2
+        start = int(rng.integers(0, 512 ** 3 - half))
+        slab = synth.grid_points_at(512, np.arange(start, start + half, dtype=np.int64))
+        pool = inputs[k][2]
+        near = pool[rng.integers(0, len(pool), size=int(n) - half)]
+        x = np.ascontiguousarray(np.concatenate([slab, near]))
+        y = np.full(int(n), np.nan, dtype=np.float32)
+        reqs.append((k, x, y, srv.submit(ms[k][0], ms[k][1], x, y)))
+    stats = [srv.wait(t) for (_, _, _, t) in reqs]
+    info = srv.stats()
+    say(f"  batches={info['batches']} max_batch={info['max_batch_requests']} "
+        f"peak={info['peak_reserved_bytes']}")
+    assert info["completed"] == n_req and info["reserved_bytes"] == 0
+    for (k, x, y, _), st in zip(reqs, stats):
+        assert st["n"] == len(x)
+        assert np.array_equal(y, alone(ms[k][0], ms[k][1], x, "bf16")), \
+            f"request of {len(x)} points (model {k}) differs from the same query alone"
+    for i in np.argsort(sizes)[:2]:
+        k, x, y, _ = reqs[i]
+        ref = oracle.parse_blob(inputs[k][0])
+        d = oracle.lookup_depth(x, inputs[k][1], 8)
+        err = np.abs(y.astype(np.float64) - oracle.forward(ref, x, d)).max()
+        say(f"  request of {len(x)} points vs the oracle: max |err| {err:.2e}")
+        assert err <= TOL["bf16"]
+    srv.close()
+
+
+def test_one_waiter_per_ticket(models):
+    """A second wait on a ticket while another thread waits on it is
+    rejected (the request is freed by exactly one waiter)."""
+    import threading
+    srv = sand.Server(0, budget_bytes=256 << 20, precision="bf16", n_streams=2)
+    x = request_points(0, 3_000_000, seed=12)
+    y = np.empty(len(x), dtype=np.float32)
+    t = srv.submit(models[0][1], models[0][3], x, y)
+    got = {}
+
+    def first():
+        got["st"] = srv.wait(t, timeout=30.0)
+
+    th = threading.Thread(target=first)
+    th.start()
+    th.join(0.001)
+    with pytest.raises(sand.SandError) as e:
+        srv.wait(t, timeout=30.0)
+    assert e.value.status == sand.sand.ERR_INVALID
+    th.join()
+    assert got["st"]["n"] == len(x)
+    assert np.array_equal(y, alone(models[0][1], models[0][3], x, "bf16"))
+    srv.close()
