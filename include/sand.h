@@ -232,6 +232,24 @@ sand_status sand_query(sand_model model, sand_depthmap map,
                        const float* xyz_dev, int64_t n, float* sdf_dev,
                        const sand_query_opts* opts, void* hip_stream);
 
+/* sand_query for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): it
+ * calls no hipMalloc, hipFree or allocating library routine. The scratch
+ * that sand_query allocates (or takes as opts.workspace) is instead a 64 MiB
+ * device array inside the library, one copy per GPU, held until the process
+ * ends; the caller still owns xyz_dev, sdf_dev and the opts buffers.
+ *  n:    at most 13,373,120 (sand_query_workspace_size(n) <= 64 MiB).
+ *  opts: as sand_query, except that opts.workspace must be NULL and DYNAMIC
+ *        mode runs only without compaction (dynamic_checkpoint = -1).
+ * All calls on one GPU share its array: two calls that overlap in time on
+ * one GPU (any streams) race, so the caller orders them. Results are
+ * sand_query's, bit for bit (the same kernels).
+ * Errors as sand_query, plus SAND_ERR_INVALID for n above the limit or a
+ * workspace, SAND_ERR_UNSUPPORTED for dynamic mode with compaction. */
+sand_status sand_query_noalloc(sand_model model, sand_depthmap map,
+                               const float* xyz_dev, int64_t n, float* sdf_dev,
+                               const sand_query_opts* opts, void* hip_stream);
+
 /* sand_query, instrumented: records HIP events on `hip_stream` between the
  * phases, waits for the query to finish, and stores the device time of each
  * phase in phase_ms (host float[5]): [0] depth lookup and histogram, [1]

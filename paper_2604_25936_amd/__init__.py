@@ -7,11 +7,11 @@ This package is the Python binding of that library.
 """
 
 from .sand import (Model, DepthMap, Server, SandError, load_model, build_depthmap,
-                   construct_depthmap, construct_octree, query,
+                   construct_depthmap, construct_octree, query, query_noalloc,
                    query_timed, query_grad, query_workspace_size,
                    query_grad_workspace_size, library, PRECISIONS, MODES)
 
 __all__ = ["Model", "DepthMap", "Server", "SandError", "load_model", "build_depthmap",
-           "construct_depthmap", "construct_octree", "query",
+           "construct_depthmap", "construct_octree", "query", "query_noalloc",
            "query_timed", "query_grad", "query_workspace_size",
            "query_grad_workspace_size", "library", "PRECISIONS", "MODES"]

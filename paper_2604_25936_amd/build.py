@@ -19,7 +19,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # the kernel sources first (the forward ones take longest)
 SOURCES = ["tmlp_sine.hip", "tmlp_finer.hip", "adjoint_sine.hip", "adjoint_finer.hip", "tmlp.hip",
-           "adjoint.hip", "lookup.hip", "mapbuild.hip", "octree.hip", "api.cpp", "server.cpp"]
+           "adjoint.hip", "lookup.hip", "mapbuild.hip", "octree.hip", "api.cpp", "server.cpp",
+           "noalloc.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument"]

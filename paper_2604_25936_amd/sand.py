@@ -87,6 +87,7 @@ def library():
             "sand_query_workspace_size": (SZ, [I64]),
             "sand_query_grad_workspace_size": (SZ, [P, I64, I32]),
             "sand_query": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P]),
+            "sand_query_noalloc": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P]),
             "sand_query_timed": (I32, [P, P, P, I64, P, ctypes.POINTER(QueryOpts), P,
                                        ctypes.POINTER(ctypes.c_float)]),
             "sand_query_grad": (I32, [P, P, P, I64, P, P, P, ctypes.POINTER(QueryOpts), P]),
@@ -290,6 +291,26 @@ def query(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_dep
               dynamic_checkpoint)
     _check(library().sand_query(model.handle, None if dmap is None else dmap.handle, _ptr(xyz), n,
                                 _ptr(out), ctypes.byref(o), _stream(stream)))
+    return out
+
+
+def query_noalloc(model, dmap, xyz, out=None, precision="fp32", mode="adaptive", max_depth=0,
+                  forced_depth=None, depth_out=None, workspace=None, stream=None, dynamic_r=0.0,
+                  dynamic_checkpoint=0):
+    """query() through sand_query_noalloc: the library allocates nothing (its
+    scratch is a fixed device array; at most 13,373,120 points, no
+    workspace, dynamic mode only with dynamic_checkpoint=-1). Pass ``out``
+    to keep this call free of torch allocations too."""
+    import torch
+    _check_points(xyz)
+    n = xyz.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xyz.device)
+    o = _opts(precision, mode, max_depth, forced_depth, depth_out, workspace, dynamic_r,
+              dynamic_checkpoint)
+    _check(library().sand_query_noalloc(model.handle, None if dmap is None else dmap.handle,
+                                        _ptr(xyz), n, _ptr(out), ctypes.byref(o),
+                                        _stream(stream)))
     return out
 
 

@@ -68,7 +68,7 @@ def test_abi_under_asan_ubsan(tmp_path):
              "-Xarch_host", "-fno-sanitize-recover=all", "-I", CSRC]
     host = []
     procs = []
-    for src in ("api.cpp", "server.cpp"):
+    for src in ("api.cpp", "server.cpp", "noalloc.cpp"):
         o = str(tmp_path / (src + ".o"))
         host.append(o)
         procs.append(subprocess.Popen([HIPCC, *flags, "-c", os.path.join(CSRC, src), "-o", o],
