@@ -36,16 +36,45 @@ namespace {
 
 using namespace mfma;
 
-// Bytes of stashed cosines per lane per output block.
+// Bytes of stashed cosines per lane per output block, and the vector
+// stores that write them.
 template <int PREC>
 constexpr int stash_lane_bytes() {
   return PREC == PREC_FP32 ? 16 : 32;
 }
+template <int PREC>
+constexpr int stash_stores() {
+  return PREC == PREC_FP32 ? 1 : 2;
+}
+
+// A operands read ahead of their MFMA in the adjoint's product chains.
+constexpr int kAdjPF = 4;
+
+// v, opaque to the compiler: what is derived from it is computed where it is
+// used instead of being hoisted and kept live (or spilled) across the loops.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// A wavefront's stash: cosines of (layer j, block rb) at byte offset
+// ((j - 1) RB + rb) 64 LB + lane LB of its region (LB bytes per lane). It is
+// addressed as a buffer (uniform base and block offset in scalar registers,
+// the lane's offset in one vector register) so that no per-lane 64-bit
+// address of any block has to stay live across the tile loop.
+struct Stash {
+  __amdgpu_buffer_rsrc_t rsrc;
+  int voff;   // lane * LB
+};
 
 template <int PREC>
-__device__ __forceinline__ void stash_put(char* p, const float (&c)[Tr<PREC>::NR]) {
+__device__ __forceinline__ void stash_put(const Stash& st, int soff,
+                                          const float (&c)[Tr<PREC>::NR]) {
   if constexpr (PREC == PREC_FP32) {
-    *(f32x4*)p = f32x4{c[0], c[1], c[2], c[3]};
+    const f32x4 v = f32x4{c[0], c[1], c[2], c[3]};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), st.rsrc, st.voff, soff, 0);
   } else {
     using V = typename Tr<PREC>::V;
     V lo, hi;
@@ -54,20 +83,24 @@ __device__ __forceinline__ void stash_put(char* p, const float (&c)[Tr<PREC>::NR
       lo[k] = (typename Tr<PREC>::E)c[k];
       hi[k] = (typename Tr<PREC>::E)c[8 + k];
     }
-    *(V*)p = lo;
-    *(V*)(p + 16) = hi;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, lo), st.rsrc, st.voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, hi), st.rsrc, st.voff + 16,
+                                           soff, 0);
   }
 }
 
 template <int PREC>
-__device__ __forceinline__ void stash_get(const char* p, float (&c)[Tr<PREC>::NR]) {
+__device__ __forceinline__ void stash_get(const Stash& st, int soff, float (&c)[Tr<PREC>::NR]) {
   if constexpr (PREC == PREC_FP32) {
-    const f32x4 v = *(const f32x4*)p;
+    const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff,
+                                                                                    soff, 0));
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] = v[k];
   } else {
     using V = typename Tr<PREC>::V;
-    const V lo = *(const V*)p, hi = *(const V*)(p + 16);
+    const V lo = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff, soff, 0));
+    const V hi =
+        __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff + 16, soff, 0));
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       c[k] = (float)lo[k];
@@ -101,7 +134,7 @@ template <int PREC, int KS, int KEEP, int ACT>
 __device__ __forceinline__ void fwd_epilogue(float kf, const char* tails, int g, int rb,
                                              const typename Tr<PREC>::Acc& acc,
                                              typename Tr<PREC>::V (&out)[KS], float& s0,
-                                             float& s1, char* stash) {
+                                             float& s1, const Stash& stash, int soff) {
   using T = Tr<PREC>;
   float h[T::NR], cs[T::NR];
 #pragma unroll
@@ -117,12 +150,15 @@ __device__ __forceinline__ void fwd_epilogue(float kf, const char* tails, int g,
       s0 = fmaf(ta[k], h[e], s0);
       s1 = fmaf(tb[k], h[e], s1);
     }
+    // one group of four at a time: computing every element's factors first
+    // would hold them all in registers at once
+    if constexpr (ACT == ACT_FINER) __builtin_amdgcn_sched_barrier(0);
   }
   if constexpr (KEEP == FE_REGS) {
     T::template store<KS>(out, rb, cs);
   } else {
     T::template store<KS>(out, rb, h);
-    if constexpr (KEEP == FE_STASH) stash_put<PREC>(stash, cs);
+    if constexpr (KEEP == FE_STASH) stash_put<PREC>(stash, soff, cs);
   }
   asm volatile("" ::"v"(s0), "v"(s1));
   pin_out<PREC, KS>(out, rb);
@@ -199,69 +235,77 @@ struct AdjCfg {
   static constexpr int STASH_WL = C::RB * 64 * stash_lane_bytes<PREC>();
 };
 
-// Per-wavefront view of the stash: cosines of (layer j, block rb).
+// Offset of the cosines of (layer j, block rb) in a wavefront's stash.
 template <int PREC, int WP>
-__device__ __forceinline__ char* stash_at(char* base, int j, int rb) {
-  return base + ((size_t)(j - 1) * Cfg<PREC, WP>::RB + rb) * 64 * stash_lane_bytes<PREC>();
+__device__ __forceinline__ int stash_at(int j, int rb) {
+  return ((j - 1) * Cfg<PREC, WP>::RB + rb) * 64 * stash_lane_bytes<PREC>();
 }
 
 // One forward hidden layer j: in -> out, cosines stashed, or (last: the
 // tile's exit layer) packed into out; returns the tail partial sums.
 template <int PREC, int WP, int ACT>
-__device__ __forceinline__ void adj_fwd_layer(float kf, const char* __restrict__ hidden, char* ring,
+__device__ __forceinline__ void adj_fwd_layer(float kf, __amdgpu_buffer_rsrc_t hidden, char* ring,
                                               int wave,
                                               int lane, int g, int& c, int nc, int j, bool last,
                                               const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
                                               typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
-                                              char* stash, float& s0, float& s1) {
+                                              const Stash& stash, float& s0, float& s1) {
   using C = Cfg<PREC, WP>;
   using A = AdjCfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
   s0 = s1 = 0.0f;
+  // lane-derived values (addresses, the constant bias operand) are rebuilt
+  // per layer from opaque copies rather than kept live across the tile loop
+  asm volatile("" : "+v"(lane), "+v"(g));
   const V bb = T::bias_b(g);
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb) {
     const bool pre = c + 1 < nc;
     if (pre)
-      load_chunk<C::CH, C::NW>(hidden + (size_t)(c + 1) * C::CH, ring + ((c + 1) & 1) * A::SLOT,
-                               wave, lane);
+      load_chunk_buf<C::CH, C::NW>(hidden, (c + 1) * C::CH, ring + ((c + 1) & 1) * A::SLOT, wave,
+                                   lane);
     const char* slot = ring + (c & 1) * A::SLOT;
     // bias step first, then the K steps: the forward kernel's order, so the
-    // recomputed values are bit-identical to a plain query
-    typename T::Acc acc = T::mma(*(const V*)(slot + (C::KS * 64 + lane) * T::VB), bb,
-                                 typename T::Acc{});
-#pragma unroll
-    for (int s = 0; s < C::KS; ++s)
-      acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
+    // recomputed values are bit-identical to a plain query (the bias tile
+    // follows the KS weight tiles in the chunk)
+    const typename T::Acc acc = mma_chain<PREC, C::KS + 1, kAdjPF>(
+        slot, lane, [](int s) { return s == 0 ? C::KS : s - 1; },
+        [&](int s) -> V { return s == 0 ? bb : in[s - 1]; });
     if (last)
       fwd_epilogue<PREC, C::KS, FE_REGS, ACT>(kf, slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
-                                              nullptr);
+                                              stash, 0);
     else
       fwd_epilogue<PREC, C::KS, FE_STASH, ACT>(kf, slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
-                                               stash_at<PREC, WP>(stash, j, rb));
-    if (pre) wait_chunk();
+                                               stash, stash_at<PREC, WP>(j, rb));
+    // the next chunk has landed once only this block's stash stores (issued
+    // after its copy) may be outstanding
+    if (pre) wait_vm(last ? 0 : stash_stores<PREC>());
     __syncthreads();
     ++c;
   }
 }
 
-// One backward layer j (j >= 2): in = delta'_j -> out = delta'_{j-1}, or the
-// input gradient when j == 2. Layer 1's cosines are recomputed from the
-// point (l1: the layer-1 chunks in LDS): its product is four inputs deep.
-template <int PREC, int WP, int ACT>
-__device__ __forceinline__ void adj_bwd_layer(float kf1, const char* __restrict__ bwd, char* ring,
+// One backward layer j (j >= 2): in = delta'_j -> out = delta'_{j-1} with
+// the stashed cosines of layer j - 1, or (FIRST: j == 2) the input gradient,
+// with layer 1's cosines recomputed from the point (l1: the layer-1 chunks
+// in LDS; its product is four inputs deep) and `out` untouched. The two
+// forms are separate copies so that neither holds the other's registers.
+template <int PREC, int WP, int ACT, bool FIRST>
+__device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t bwd, char* ring,
                                               int wave,
                                               int lane, int g, int& c, int nc, int d, int j,
                                               const char* l1, float px, float py, float pz,
                                               const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
                                               typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
-                                              char* stash, float v0, float v1, const char* w1t,
+                                              const Stash& stash, float v0, float v1,
+                                              const char* w1t,
                                               float (&gx)[3]) {
   using C = Cfg<PREC, WP>;
   using A = AdjCfg<PREC, WP>;
   using T = Tr<PREC>;
   using V = typename T::V;
+  asm volatile("" : "+v"(lane), "+v"(g));   // see adj_fwd_layer
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb) {
     const bool pre = c + 1 < nc;
@@ -269,16 +313,14 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, const char* __restrict_
       // chunks run layer d, d-1, ..., 2 and blocks 0..RB-1 within a layer
       const int c1 = c + 1;
       const int jn = d - c1 / C::RB, rn = c1 % C::RB;
-      load_chunk<C::CH_B, C::NW>(bwd + ((size_t)(jn - 2) * C::RB + rn) * C::CH_B,
-                                 ring + (c1 & 1) * A::SLOT, wave, lane);
+      load_chunk_buf<C::CH_B, C::NW>(bwd, ((jn - 2) * C::RB + rn) * C::CH_B,
+                                     ring + (c1 & 1) * A::SLOT, wave, lane);
     }
     const char* slot = ring + (c & 1) * A::SLOT;
-    typename T::Acc acc = {};
-#pragma unroll
-    for (int s = 0; s < C::KS; ++s)
-      acc = T::mma(*(const V*)(slot + (s * 64 + lane) * T::VB), in[s], acc);
+    const typename T::Acc acc = mma_chain<PREC, C::KS, kAdjPF>(
+        slot, lane, [](int s) { return s; }, [&](int s) -> V { return in[s]; });
     float cs[T::NR];
-    if (j == 2) {
+    if constexpr (FIRST) {
       typename T::Acc z = {};
 #pragma unroll
       for (int st = 0; st < T::L1S; ++st)
@@ -286,10 +328,10 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, const char* __restrict_
 #pragma unroll
       for (int e = 0; e < T::NR; ++e) cs[e] = act_slope<ACT>(z[e], act_arg<ACT>(z[e], kf1), kf1);
     } else {
-      stash_get<PREC>(stash_at<PREC, WP>(stash, j - 1, rb), cs);
+      stash_get<PREC>(stash, stash_at<PREC, WP>(j - 1, rb), cs);
     }
     bwd_epilogue<PREC, C::KS>((const float*)(slot + C::TAIL_OFF_B), T::BM, g, rb, acc, v0, v1, cs,
-                              out, j == 2, w1t, gx);
+                              out, FIRST, w1t, gx);
     if (pre) wait_chunk();
     __syncthreads();
     ++c;
@@ -309,22 +351,33 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
   char* l1 = lds + 2 * A::SLOT;
   char* w1t = l1 + C::L1B;
   float* ust = (float*)(w1t + A::W1T);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int g = T::grp(lane), col = T::col(lane);
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const QueryArgs& q = a.q;
 
   __shared__ Plan splan;   // the plan's bucket bounds, read per tile
+  // Each lane's point (x, y, z, dy) and index for the current tile, parked in
+  // LDS between layer 1 and their next use (layer 1 again, at the end of the
+  // backward pass; the stores at the end of the tile), so that they hold no
+  // registers through the hidden layers.
+  __shared__ f32x4 spt[C::NT];
+  __shared__ int32_t sgi[C::NT];
   for (int i = tid; i < C::L1B / 16; i += C::NT) ((uint4*)l1)[i] = ((const uint4*)q.m.chunks)[i];
   for (int i = tid; i < A::W1T / 16; i += C::NT) ((uint4*)w1t)[i] = ((const uint4*)a.w1t)[i];
   if (q.plan)
     for (int i = tid; i < (int)(sizeof(Plan) / 8); i += C::NT)
       ((int64_t*)&splan)[i] = ((const int64_t*)q.plan)[i];
   __syncthreads();
-  const char* hidden = q.m.chunks + C::L1B;
   const int L = q.m.L;
+  // the weight streams as buffers (uniform bases, 32-bit lane offsets)
+  const __amdgpu_buffer_rsrc_t hidden = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(q.m.chunks + C::L1B), 0, (L - 1) * C::RB * C::CH, kBufferWord3);
+  const __amdgpu_buffer_rsrc_t bwd = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<char*>(a.bwd), 0, (L - 1) * C::RB * C::CH_B, kBufferWord3);
   const int64_t total = q.plan ? splan.total_tiles : (q.n + Q - 1) / Q;
-  char* stash = a.stash + (size_t)blockIdx.x * a.stash_wg + (size_t)wave * L * A::STASH_WL +
-                lane * stash_lane_bytes<PREC>();
+  const __amdgpu_buffer_rsrc_t stash_rs = __builtin_amdgcn_make_buffer_rsrc(
+      a.stash + (size_t)blockIdx.x * a.stash_wg + (size_t)wave * L * A::STASH_WL, 0,
+      L * A::STASH_WL, kBufferWord3);
   float* uw = ust + wave * kMaxLayers * NQ * 2;   // [layer][point][2]
 
   // Tiles (deepest first) are drawn one at a time from a counter, so a
@@ -338,6 +391,13 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     const int64_t tile = drawn;
     __syncthreads();
     if (tile >= total) break;
+    // Lane-derived values are rebuilt per tile from an opaque copy of the
+    // lane index: kept live across the tile loop they would not fit the
+    // register budget beside the two activation buffers.
+    int lane = tid & 63;
+    asm volatile("" : "+v"(lane));
+    const int g = T::grp(lane), col = T::col(lane);
+    const Stash stash{stash_rs, lane * stash_lane_bytes<PREC>()};
     int d;
     int64_t start, cnt;
     if (q.plan) {
@@ -369,6 +429,8 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       pz = p[2];
       dy = a.dy ? a.dy[gi] : 1.0f;
     }
+    spt[tid] = f32x4{px, py, pz, dy};
+    sgi[tid] = ok ? (int32_t)gi : -1;
 
     // ---------------- forward recompute with stash ----------------
     V actA[C::KS], actB[C::KS];
@@ -382,10 +444,10 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
         acc = T::mma1(T::l1_a(ch, st, lane), T::l1_b(st, g, px, py, pz), acc);
       if (d == 1)
         fwd_epilogue<PREC, C::KS, FE_REGS, ACT>(q.m.kf[0], ch + T::L1S * T::L1AB, g, rb, acc, actA,
-                                                s0, s1, nullptr);
+                                                s0, s1, stash, 0);
       else
         fwd_epilogue<PREC, C::KS, FE_NONE, ACT>(q.m.kf[0], ch + T::L1S * T::L1AB, g, rb, acc, actA,
-                                                s0, s1, nullptr);
+                                                s0, s1, stash, 0);
     }
     float u0 = T::lane_sum(s0) + q.m.c0[0], u1 = T::lane_sum(s1) + q.m.c1[0];
     float y = fmaf(u0, u1, 0.0f);
@@ -396,7 +458,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     const int nc = (d - 1) * C::RB;
     int c = 0;
     if (nc > 0) {
-      load_chunk<C::CH, C::NW>(hidden, ring, wave, lane);
+      load_chunk_buf<C::CH, C::NW>(hidden, 0, ring, wave, lane);
       wait_chunk();
       __syncthreads();
     }
@@ -415,7 +477,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
         uw[((j - 1) * NQ + col) * 2 + 1] = u1;
       }
     }
-    if (q.sdf && g == 0 && ok) q.sdf[gi] = y;
+    if (q.sdf && g == 0 && ok) q.sdf[sgi[opaque(tid)]] = y;
 
     // ---------------- backward ----------------
     // exit tail of layer d: delta'_d = cos_d * (u1 a0 + u0 a1), into actA;
@@ -441,27 +503,44 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     const int ncb = (d - 1) * C::RB;
     c = 0;
     if (ncb > 0) {
-      load_chunk<C::CH_B, C::NW>(a.bwd + (size_t)(d - 2) * C::RB * C::CH_B, ring, wave, lane);
+      load_chunk_buf<C::CH_B, C::NW>(bwd, (d - 2) * C::RB * C::CH_B, ring, wave, lane);
       wait_chunk();
       __syncthreads();
     }
-    for (int j = d; j >= 2; j -= 2) {
-      adj_bwd_layer<PREC, WP, ACT>(q.m.kf[0], a.bwd, ring, wave, lane, g, c, ncb, d, j, l1, px, py,
-                                   pz, actA, actB, stash,
-                              uw[((j - 2) * NQ + col) * 2], uw[((j - 2) * NQ + col) * 2 + 1], w1t,
-                              gx);
-      if (j - 1 < 2) break;
-      adj_bwd_layer<PREC, WP, ACT>(q.m.kf[0], a.bwd, ring, wave, lane, g, c, ncb, d, j - 1, l1, px,
-                                   py, pz, actB, actA, stash,
-                              uw[((j - 3) * NQ + col) * 2], uw[((j - 3) * NQ + col) * 2 + 1], w1t,
-                              gx);
+    // layers d..3 pass delta' on (actA -> actB -> actA ...); layer 2 then
+    // ends in the input gradient from whichever buffer holds delta'_2
+    for (int j = d; j >= 3; j -= 2) {
+      adj_bwd_layer<PREC, WP, ACT, false>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, j, l1, px,
+                                          py, pz, actA, actB, stash,
+                                          uw[((j - 2) * NQ + col) * 2],
+                                          uw[((j - 2) * NQ + col) * 2 + 1], w1t, gx);
+      if (j - 1 < 3) break;
+      adj_bwd_layer<PREC, WP, ACT, false>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, j - 1, l1,
+                                          px, py, pz, actB, actA, stash,
+                                          uw[((j - 3) * NQ + col) * 2],
+                                          uw[((j - 3) * NQ + col) * 2 + 1], w1t, gx);
+    }
+    if (d >= 2) {
+      const float v0 = uw[col * 2], v1 = uw[col * 2 + 1];
+      const f32x4 pt = spt[opaque(tid)];
+      if (((d - 2) & 1) == 0)
+        adj_bwd_layer<PREC, WP, ACT, true>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, 2, l1,
+                                           pt[0], pt[1], pt[2], actA, actB, stash, v0, v1, w1t,
+                                           gx);
+      else
+        adj_bwd_layer<PREC, WP, ACT, true>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, 2, l1,
+                                           pt[0], pt[1], pt[2], actB, actA, stash, v0, v1, w1t,
+                                           gx);
     }
     const float gxs = T::lane_sum(gx[0]), gys = T::lane_sum(gx[1]), gzs = T::lane_sum(gx[2]);
-    if (g == 0 && ok) {
-      float* o = a.grad + 3 * gi;
-      o[0] = dy * gxs;
-      o[1] = dy * gys;
-      o[2] = dy * gzs;
+    const int tl = opaque(tid);
+    const int32_t go = sgi[tl];
+    if (g == 0 && go >= 0) {
+      const float dyo = spt[tl][3];
+      float* o = a.grad + 3 * (int64_t)go;
+      o[0] = dyo * gxs;
+      o[1] = dyo * gys;
+      o[2] = dyo * gzs;
     }
   }
 }
