@@ -36,16 +36,65 @@ namespace {
 
 using namespace mfma;
 
-// Bytes of stashed cosines per lane per output block, and the vector
-// stores that write them.
+// Bytes of stashed cosines per lane per output block.
 template <int PREC>
 constexpr int stash_lane_bytes() {
   return PREC == PREC_FP32 ? 16 : 32;
 }
-template <int PREC>
-constexpr int stash_stores() {
-  return PREC == PREC_FP32 ? 1 : 2;
+
+// MFMA chain over NS K steps: step s multiplies A tile tile(s) of an LDS
+// slot (64 lanes x VB bytes per tile) by the B operand b(s). The A operands
+// are read PF steps ahead of their MFMA; the scheduling groups keep the
+// compiler from hoisting more reads (each holds registers) or sinking each
+// read to its MFMA (which would make every MFMA wait a full LDS round trip).
+template <int PREC, int NS, int PF, class Tile, class BOp>
+__device__ __forceinline__ typename Tr<PREC>::Acc mma_chain(const char* slot, int lane, Tile tile,
+                                                            BOp b) {
+  using T = Tr<PREC>;
+  using V = typename T::V;
+  constexpr int P = NS < PF ? NS : PF;
+  auto a_of = [&](int s) -> V { return *(const V*)(slot + (tile(s) * 64 + lane) * T::VB); };
+  V a[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) a[s] = a_of(s);
+  typename T::Acc acc = {};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const V cur = a[s % P];
+    if (s + P < NS) a[s % P] = a_of(s + P);
+    acc = T::mma(cur, b(s), acc);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x100, P, 0);
+#pragma unroll
+  for (int s = 0; s < NS - P; ++s) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, P, 0);
+  return acc;
 }
+
+// load_chunk from byte src_off (uniform) of a buffer resource: each lane's
+// source is a 32-bit offset formed at the load, so no 64-bit per-lane
+// address stays live between chunks (this kernel's register budget is
+// tighter than the forward kernel's).
+template <int BYTES, int NW>
+__device__ __forceinline__ void load_chunk_buf(__amdgpu_buffer_rsrc_t src, int src_off, char* dst,
+                                               int wave, int lane) {
+  constexpr int NP = BYTES / 16;
+  constexpr int WL = (NP + 64 * NW - 1) / (64 * NW);
+#pragma unroll
+  for (int k = 0; k < WL; ++k) {
+    const int q = k * NW + wave;
+    const int piece = q * 64 + lane;
+    if (q * 64 < NP && piece < NP)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(src, lds_ptr(dst + q * 1024), 16, piece * 16,
+                                               src_off, 0, 0);
+  }
+}
+
+// Fourth word of a raw buffer resource on gfx9 (32-bit data format).
+constexpr int kBufferWord3 = 0x00020000;
 
 // A operands read ahead of their MFMA in the adjoint's product chains.
 constexpr int kAdjPF = 4;
@@ -126,7 +175,10 @@ __device__ __forceinline__ void pin_out(const typename Tr<PREC>::V (&out)[KS], i
 // packs the cosines into out instead of the activations (the tile's last
 // layer, whose activations feed nothing and whose cosines the backward
 // needs first).
-enum FwdKeep { FE_STASH, FE_NONE, FE_REGS };
+// FE_F32 hands the cosines back in FP32 (cs_out) and packs nothing (layer 1
+// of a depth-1 tile in the 16-bit precisions: its cosines are the whole
+// gradient, so they are kept unrounded).
+enum FwdKeep { FE_STASH, FE_NONE, FE_REGS, FE_F32 };
 
 // Forward epilogue: sine, tail partial sums, and the slopes sigma'(z) / omega
 // ("cosines") as FwdKeep says.
@@ -134,7 +186,8 @@ template <int PREC, int KS, int KEEP, int ACT>
 __device__ __forceinline__ void fwd_epilogue(float kf, const char* tails, int g, int rb,
                                              const typename Tr<PREC>::Acc& acc,
                                              typename Tr<PREC>::V (&out)[KS], float& s0,
-                                             float& s1, const Stash& stash, int soff) {
+                                             float& s1, const Stash& stash, int soff,
+                                             float* cs_out = nullptr) {
   using T = Tr<PREC>;
   float h[T::NR], cs[T::NR];
 #pragma unroll
@@ -154,7 +207,12 @@ __device__ __forceinline__ void fwd_epilogue(float kf, const char* tails, int g,
     // would hold them all in registers at once
     if constexpr (ACT == ACT_FINER) __builtin_amdgcn_sched_barrier(0);
   }
-  if constexpr (KEEP == FE_REGS) {
+  if constexpr (KEEP == FE_F32) {
+#pragma unroll
+    for (int e = 0; e < T::NR; ++e) cs_out[e] = cs[e];
+    asm volatile("" ::"v"(s0), "v"(s1));
+    return;
+  } else if constexpr (KEEP == FE_REGS) {
     T::template store<KS>(out, rb, cs);
   } else {
     T::template store<KS>(out, rb, h);
@@ -278,9 +336,13 @@ __device__ __forceinline__ void adj_fwd_layer(float kf, __amdgpu_buffer_rsrc_t h
     else
       fwd_epilogue<PREC, C::KS, FE_STASH, ACT>(kf, slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
                                                stash, stash_at<PREC, WP>(j, rb));
-    // the next chunk has landed once only this block's stash stores (issued
-    // after its copy) may be outstanding
-    if (pre) wait_vm(last ? 0 : stash_stores<PREC>());
+    // The next chunk's copy must have landed; this waits for the block's
+    // stash stores too. A count that left those stores outstanding is not
+    // safe: vector-memory loads and stores are not counted down in issue
+    // order with respect to each other, so it can pass with a chunk piece
+    // still in flight (seen as rare wrong gradients of the FINER FP32 form
+    // at width 352).
+    if (pre) wait_chunk();
     __syncthreads();
     ++c;
   }
@@ -442,10 +504,25 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
 #pragma unroll
       for (int st = 0; st < T::L1S; ++st)
         acc = T::mma1(T::l1_a(ch, st, lane), T::l1_b(st, g, px, py, pz), acc);
-      if (d == 1)
+      if (T::VB == 16 && d == 1) {
+        if constexpr (T::VB == 16) {
+          // FP32 cosines of block rb: four vectors at 4 rb.. of the pair
+          // (actA, actB), which no hidden layer needs in a depth-1 tile
+          float cf[T::NR];
+          fwd_epilogue<PREC, C::KS, FE_F32, ACT>(q.m.kf[0], ch + T::L1S * T::L1AB, g, rb, acc,
+                                                 actA, s0, s1, stash, 0, cf);
+#pragma unroll
+          for (int i = 0; i < T::NR / 4; ++i) {
+            const V v = __builtin_bit_cast(V, f32x4{cf[4 * i], cf[4 * i + 1], cf[4 * i + 2],
+                                                    cf[4 * i + 3]});
+            const int qv = (T::NR / 4) * rb + i;
+            if (qv < C::KS) actA[qv] = v; else actB[qv - C::KS] = v;
+          }
+        }
+      } else if (d == 1) {
         fwd_epilogue<PREC, C::KS, FE_REGS, ACT>(q.m.kf[0], ch + T::L1S * T::L1AB, g, rb, acc, actA,
                                                 s0, s1, stash, 0);
-      else
+      } else
         fwd_epilogue<PREC, C::KS, FE_NONE, ACT>(q.m.kf[0], ch + T::L1S * T::L1AB, g, rb, acc, actA,
                                                 s0, s1, stash, 0);
     }
@@ -490,7 +567,23 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
         for (int rb = 0; rb < C::RB; ++rb) {
           const typename T::Acc zero = {};
           float cs[T::NR];
-          cos_from_regs<PREC, C::KS>(cosv, rb, cs);
+          bool f32 = false;
+          if constexpr (T::VB == 16) {
+            if (d == 1) {
+#pragma unroll
+              for (int i = 0; i < T::NR / 4; ++i) {
+                const int qv = (T::NR / 4) * rb + i;
+                const f32x4 v =
+                    __builtin_bit_cast(f32x4, qv < C::KS ? actA[qv] : actB[qv - C::KS]);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) cs[4 * i + k] = v[k];
+              }
+              f32 = true;
+            }
+          }
+          if (!f32) {
+            cos_from_regs<PREC, C::KS>(cosv, rb, cs);
+          }
           bwd_epilogue<PREC, C::KS>(tl + T::BM * rb, WP, g, rb, zero, u0, u1, cs, actA, d == 1,
                                     w1t, gx);
         }

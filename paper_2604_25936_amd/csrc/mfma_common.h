@@ -246,38 +246,6 @@ struct Cfg {
                 "chunks are whole 16-byte pieces");
 };
 
-// MFMA chain over NS K steps: step s multiplies A tile tile(s) of an LDS
-// slot (64 lanes x VB bytes per tile) by the B operand b(s). The A operands
-// are read PF steps ahead of their MFMA; the scheduling groups keep the
-// compiler from hoisting more reads (each holds registers) or sinking each
-// read to its MFMA (which would make every MFMA wait a full LDS round trip).
-template <int PREC, int NS, int PF, class Tile, class BOp>
-__device__ __forceinline__ typename Tr<PREC>::Acc mma_chain(const char* slot, int lane, Tile tile,
-                                                            BOp b) {
-  using T = Tr<PREC>;
-  using V = typename T::V;
-  constexpr int P = NS < PF ? NS : PF;
-  auto a_of = [&](int s) -> V { return *(const V*)(slot + (tile(s) * 64 + lane) * T::VB); };
-  V a[P];
-#pragma unroll
-  for (int s = 0; s < P; ++s) a[s] = a_of(s);
-  typename T::Acc acc = {};
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const V cur = a[s % P];
-    if (s + P < NS) a[s % P] = a_of(s + P);
-    acc = T::mma(cur, b(s), acc);
-  }
-  __builtin_amdgcn_sched_group_barrier(0x100, P, 0);
-#pragma unroll
-  for (int s = 0; s < NS - P; ++s) {
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-  }
-  __builtin_amdgcn_sched_group_barrier(0x008, P, 0);
-  return acc;
-}
-
 typedef __attribute__((address_space(3))) void lds_void;
 
 // LDS pointer of a generic pointer into a __shared__ array: the low 32 bits
@@ -308,28 +276,6 @@ __device__ __forceinline__ void load_chunk(const char* __restrict__ src, char* d
                                        0, 0);
   }
 }
-
-// load_chunk from byte src_off (uniform) of a buffer resource: each lane's
-// source is a 32-bit offset formed at the load, so no 64-bit per-lane
-// address stays live between chunks (the adjoint kernel, whose register
-// budget is tighter, streams its weights this way).
-template <int BYTES, int NW>
-__device__ __forceinline__ void load_chunk_buf(__amdgpu_buffer_rsrc_t src, int src_off, char* dst,
-                                               int wave, int lane) {
-  constexpr int NP = BYTES / 16;
-  constexpr int WL = (NP + 64 * NW - 1) / (64 * NW);
-#pragma unroll
-  for (int k = 0; k < WL; ++k) {
-    const int q = k * NW + wave;
-    const int piece = q * 64 + lane;
-    if (q * 64 < NP && piece < NP)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(src, lds_ptr(dst + q * 1024), 16, piece * 16,
-                                               src_off, 0, 0);
-  }
-}
-
-// Fourth word of a raw buffer resource on gfx9 (32-bit data format).
-constexpr int kBufferWord3 = 0x00020000;
 
 __device__ __forceinline__ void wait_chunk() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 

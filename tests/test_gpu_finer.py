@@ -277,3 +277,25 @@ def test_finer_dynamic_compaction_is_exact(prec):
         y, d = run_cp(model, x, r, prec, cp)
         assert np.array_equal(d, d0)
         assert np.array_equal(y.view(np.uint32), y0.view(np.uint32))
+
+
+@pytest.mark.parametrize("W,L", [(16, 2), (64, 4), (128, 3), (336, 3)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_finer_gradient_widths(W, L, prec):
+    """The FINER adjoint at every padded width (16 -> 64, 128, 336 -> 352),
+    adaptive and full depth, against the oracle gradient."""
+    say(f"case: FINER gradient W={W} L={L} {prec}")
+    blob = synth.write_blob(synth.siren_tmlp(500 + W, L, W, tails="mult", activation="finer"))
+    ref = oracle.parse_blob(blob)
+    model = sand.load_model(blob, 0)
+    rng = np.random.Generator(np.random.PCG64(W + 7 * L))
+    dmap = rng.integers(1, L + 1, size=(8, 8, 8)).astype(np.uint8)
+    dm = sand.build_depthmap(model, dmap)
+    x = rng.uniform(-1, 1, size=(2500, 3)).astype(np.float32)
+    xyz = torch.from_numpy(x).to(DEV)
+    g = sand.query_grad(model, dm, xyz, precision=prec).cpu().numpy().astype(np.float64)
+    check_grad(g, oracle.gradient(ref, x, oracle.lookup_depth(x, dmap, L)), prec,
+               f"FINER W={W} L={L} {prec}")
+    g = sand.query_grad(model, dm, xyz, precision=prec, mode="full").cpu().numpy()
+    check_grad(g.astype(np.float64), oracle.gradient(ref, x, np.full(len(x), L)), prec,
+               f"FINER W={W} L={L} {prec} full")
