@@ -99,14 +99,35 @@ constexpr int kBufferWord3 = 0x00020000;
 // A operands read ahead of their MFMA in the adjoint's product chains.
 constexpr int kAdjPF = 4;
 
-// v, opaque to the compiler: what is derived from it is computed where it is
-// used instead of being hoisted and kept live (or spilled) across the loops.
-__device__ __forceinline__ int opaque(int v) {
-  asm volatile("" : "+v"(v));
-  return v;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// This lane's position in its wavefront, computed afresh at each use (an asm
+// statement is neither merged with another nor hoisted out of a loop), so
+// that neither it nor the thread index is kept live, or spilled, across the
+// tile loop.
+__device__ __forceinline__ int lane_now() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
 }
 
-typedef int i32x4 __attribute__((ext_vector_type(4)));
+// Tr<PREC>::lane_sum with the exchange addresses formed from lane_now()
+// (ds_bpermute reads lane address / 4).
+template <int PREC>
+__device__ __forceinline__ float adj_lane_sum(float v) {
+  const int a = lane_now() << 2;
+  if constexpr (PREC == PREC_FP32)
+    v += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(a ^ 64, __builtin_bit_cast(int, v)));
+  return v + __builtin_bit_cast(float,
+                                __builtin_amdgcn_ds_bpermute(a ^ 128, __builtin_bit_cast(int, v)));
+}
+
+// A 64-bit value that is the same in every lane, in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 // A wavefront's stash: cosines of (layer j, block rb) at byte offset
 // ((j - 1) RB + rb) 64 LB + lane LB of its region (LB bytes per lane). It is
@@ -436,7 +457,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       const_cast<char*>(q.m.chunks + C::L1B), 0, (L - 1) * C::RB * C::CH, kBufferWord3);
   const __amdgpu_buffer_rsrc_t bwd = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<char*>(a.bwd), 0, (L - 1) * C::RB * C::CH_B, kBufferWord3);
-  const int64_t total = q.plan ? splan.total_tiles : (q.n + Q - 1) / Q;
+  const int64_t total = uniform64(q.plan ? splan.total_tiles : (q.n + Q - 1) / Q);
   const __amdgpu_buffer_rsrc_t stash_rs = __builtin_amdgcn_make_buffer_rsrc(
       a.stash + (size_t)blockIdx.x * a.stash_wg + (size_t)wave * L * A::STASH_WL, 0,
       L * A::STASH_WL, kBufferWord3);
@@ -448,16 +469,15 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
   // depth-L tile more).
   __shared__ uint32_t drawn;
   for (;;) {
-    if (tid == 0) drawn = atomicAdd(a.next_tile, 1u);
+    if (wave == 0 && lane_now() == 0) drawn = atomicAdd(a.next_tile, 1u);
     __syncthreads();
     const int64_t tile = drawn;
     __syncthreads();
     if (tile >= total) break;
-    // Lane-derived values are rebuilt per tile from an opaque copy of the
-    // lane index: kept live across the tile loop they would not fit the
-    // register budget beside the two activation buffers.
-    int lane = tid & 63;
-    asm volatile("" : "+v"(lane));
+    // Lane-derived values are rebuilt per tile from lane_now(): kept live
+    // across the tile loop they would not fit the register budget beside the
+    // two activation buffers.
+    int lane = lane_now();
     const int g = T::grp(lane), col = T::col(lane);
     const Stash stash{stash_rs, lane * stash_lane_bytes<PREC>()};
     int d;
@@ -491,8 +511,11 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       pz = p[2];
       dy = a.dy ? a.dy[gi] : 1.0f;
     }
-    spt[tid] = f32x4{px, py, pz, dy};
-    sgi[tid] = ok ? (int32_t)gi : -1;
+    {
+      const int t = wave * 64 + lane_now();
+      spt[t] = f32x4{px, py, pz, dy};
+      sgi[t] = ok ? (int32_t)gi : -1;
+    }
 
     // ---------------- forward recompute with stash ----------------
     V actA[C::KS], actB[C::KS];
@@ -526,7 +549,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
         fwd_epilogue<PREC, C::KS, FE_NONE, ACT>(q.m.kf[0], ch + T::L1S * T::L1AB, g, rb, acc, actA,
                                                 s0, s1, stash, 0);
     }
-    float u0 = T::lane_sum(s0) + q.m.c0[0], u1 = T::lane_sum(s1) + q.m.c1[0];
+    float u0 = adj_lane_sum<PREC>(s0) + q.m.c0[0], u1 = adj_lane_sum<PREC>(s1) + q.m.c1[0];
     float y = fmaf(u0, u1, 0.0f);
     if (g == 0) {
       uw[col * 2] = u0;
@@ -546,15 +569,15 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       else
         adj_fwd_layer<PREC, WP, ACT>(q.m.kf[1], hidden, ring, wave, lane, g, c, nc, j, j == d, actA,
                                      actB, stash, s0, s1);
-      u0 = T::lane_sum(s0) + q.m.c0[j - 1];
-      u1 = T::lane_sum(s1) + q.m.c1[j - 1];
+      u0 = adj_lane_sum<PREC>(s0) + q.m.c0[j - 1];
+      u1 = adj_lane_sum<PREC>(s1) + q.m.c1[j - 1];
       y = fmaf(u0, u1, y);
       if (g == 0) {
         uw[((j - 1) * NQ + col) * 2] = u0;
         uw[((j - 1) * NQ + col) * 2 + 1] = u1;
       }
     }
-    if (q.sdf && g == 0 && ok) q.sdf[sgi[opaque(tid)]] = y;
+    if (q.sdf && g == 0 && ok) q.sdf[sgi[wave * 64 + lane_now()]] = y;
 
     // ---------------- backward ----------------
     // exit tail of layer d: delta'_d = cos_d * (u1 a0 + u0 a1), into actA;
@@ -615,7 +638,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     }
     if (d >= 2) {
       const float v0 = uw[col * 2], v1 = uw[col * 2 + 1];
-      const f32x4 pt = spt[opaque(tid)];
+      const f32x4 pt = spt[wave * 64 + lane_now()];
       if (((d - 2) & 1) == 0)
         adj_bwd_layer<PREC, WP, ACT, true>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, 2, l1,
                                            pt[0], pt[1], pt[2], actA, actB, stash, v0, v1, w1t,
@@ -625,8 +648,9 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
                                            pt[0], pt[1], pt[2], actB, actA, stash, v0, v1, w1t,
                                            gx);
     }
-    const float gxs = T::lane_sum(gx[0]), gys = T::lane_sum(gx[1]), gzs = T::lane_sum(gx[2]);
-    const int tl = opaque(tid);
+    const float gxs = adj_lane_sum<PREC>(gx[0]), gys = adj_lane_sum<PREC>(gx[1]),
+                gzs = adj_lane_sum<PREC>(gx[2]);
+    const int tl = wave * 64 + lane_now();
     const int32_t go = sgi[tl];
     if (g == 0 && go >= 0) {
       const float dyo = spt[tl][3];
