@@ -99,6 +99,13 @@ constexpr int kBufferWord3 = 0x00020000;
 // A operands read ahead of their MFMA in the adjoint's product chains.
 constexpr int kAdjPF = 4;
 
+// Workgroup barrier without the release fence of __syncthreads, which waits
+// for every global store of the wavefront (here: the block's stash stores,
+// which no other wavefront reads). Callers have awaited what other
+// wavefronts read after it (a weight chunk's LDS copy, with wait_chunk); the
+// memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::: "memory"); }
+
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // This lane's position in its wavefront, computed afresh at each use (an asm
@@ -159,18 +166,31 @@ __device__ __forceinline__ void stash_put(const Stash& st, int soff,
   }
 }
 
+// The raw stash words of one block: issued by stash_load, widened to FP32 by
+// stash_unpack, so that the loads can go out ahead of the weight-chunk copy
+// and be awaited without it.
+struct StashRaw {
+  i32x4 w[2];
+};
+
 template <int PREC>
-__device__ __forceinline__ void stash_get(const Stash& st, int soff, float (&c)[Tr<PREC>::NR]) {
+__device__ __forceinline__ StashRaw stash_load(const Stash& st, int soff) {
+  StashRaw r;
+  r.w[0] = __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff, soff, 0);
+  if constexpr (PREC != PREC_FP32)
+    r.w[1] = __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff + 16, soff, 0);
+  return r;
+}
+
+template <int PREC>
+__device__ __forceinline__ void stash_unpack(const StashRaw& r, float (&c)[Tr<PREC>::NR]) {
   if constexpr (PREC == PREC_FP32) {
-    const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff,
-                                                                                    soff, 0));
+    const f32x4 v = __builtin_bit_cast(f32x4, r.w[0]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] = v[k];
   } else {
     using V = typename Tr<PREC>::V;
-    const V lo = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff, soff, 0));
-    const V hi =
-        __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff + 16, soff, 0));
+    const V lo = __builtin_bit_cast(V, r.w[0]), hi = __builtin_bit_cast(V, r.w[1]);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       c[k] = (float)lo[k];
@@ -351,20 +371,21 @@ __device__ __forceinline__ void adj_fwd_layer(float kf, __amdgpu_buffer_rsrc_t h
     const typename T::Acc acc = mma_chain<PREC, C::KS + 1, kAdjPF>(
         slot, lane, [](int s) { return s == 0 ? C::KS : s - 1; },
         [&](int s) -> V { return s == 0 ? bb : in[s - 1]; });
+    // The next chunk's copy must have landed before the barrier below. The
+    // wait comes before this block's epilogue, so that it covers the previous
+    // block's stash stores (long done) rather than this one's. A count that
+    // left stores outstanding is not safe: vector-memory loads and stores are
+    // not counted down in issue order with respect to each other, so it can
+    // pass with a chunk piece still in flight (seen as rare wrong gradients
+    // of the FINER FP32 form at width 352).
+    if (pre) wait_chunk();
     if (last)
       fwd_epilogue<PREC, C::KS, FE_REGS, ACT>(kf, slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
                                               stash, 0);
     else
       fwd_epilogue<PREC, C::KS, FE_STASH, ACT>(kf, slot + C::TAIL_OFF, g, rb, acc, out, s0, s1,
                                                stash, stash_at<PREC, WP>(j, rb));
-    // The next chunk's copy must have landed; this waits for the block's
-    // stash stores too. A count that left those stores outstanding is not
-    // safe: vector-memory loads and stores are not counted down in issue
-    // order with respect to each other, so it can pass with a chunk piece
-    // still in flight (seen as rare wrong gradients of the FINER FP32 form
-    // at width 352).
-    if (pre) wait_chunk();
-    __syncthreads();
+    barrier_no_fence();
     ++c;
   }
 }
@@ -392,6 +413,12 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb) {
     const bool pre = c + 1 < nc;
+    // The block's stashed cosines are requested before the next chunk's
+    // copy: loads complete in issue order, so the wait for them (after the
+    // product chain) leaves the copy in flight. This wavefront has no
+    // stores outstanding here.
+    StashRaw raw;
+    if constexpr (!FIRST) raw = stash_load<PREC>(stash, stash_at<PREC, WP>(j - 1, rb));
     if (pre) {
       // chunks run layer d, d-1, ..., 2 and blocks 0..RB-1 within a layer
       const int c1 = c + 1;
@@ -411,7 +438,7 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
 #pragma unroll
       for (int e = 0; e < T::NR; ++e) cs[e] = act_slope<ACT>(z[e], act_arg<ACT>(z[e], kf1), kf1);
     } else {
-      stash_get<PREC>(stash, stash_at<PREC, WP>(j - 1, rb), cs);
+      stash_unpack<PREC>(raw, cs);
     }
     bwd_epilogue<PREC, C::KS>((const float*)(slot + C::TAIL_OFF_B), T::BM, g, rb, acc, v0, v1, cs,
                               out, FIRST, w1t, gx);
