@@ -166,31 +166,18 @@ __device__ __forceinline__ void stash_put(const Stash& st, int soff,
   }
 }
 
-// The raw stash words of one block: issued by stash_load, widened to FP32 by
-// stash_unpack, so that the loads can go out ahead of the weight-chunk copy
-// and be awaited without it.
-struct StashRaw {
-  i32x4 w[2];
-};
-
 template <int PREC>
-__device__ __forceinline__ StashRaw stash_load(const Stash& st, int soff) {
-  StashRaw r;
-  r.w[0] = __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff, soff, 0);
-  if constexpr (PREC != PREC_FP32)
-    r.w[1] = __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff + 16, soff, 0);
-  return r;
-}
-
-template <int PREC>
-__device__ __forceinline__ void stash_unpack(const StashRaw& r, float (&c)[Tr<PREC>::NR]) {
+__device__ __forceinline__ void stash_get(const Stash& st, int soff, float (&c)[Tr<PREC>::NR]) {
   if constexpr (PREC == PREC_FP32) {
-    const f32x4 v = __builtin_bit_cast(f32x4, r.w[0]);
+    const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff,
+                                                                                    soff, 0));
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] = v[k];
   } else {
     using V = typename Tr<PREC>::V;
-    const V lo = __builtin_bit_cast(V, r.w[0]), hi = __builtin_bit_cast(V, r.w[1]);
+    const V lo = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff, soff, 0));
+    const V hi =
+        __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(st.rsrc, st.voff + 16, soff, 0));
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       c[k] = (float)lo[k];
@@ -413,12 +400,6 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
 #pragma unroll
   for (int rb = 0; rb < C::RB; ++rb) {
     const bool pre = c + 1 < nc;
-    // The block's stashed cosines are requested before the next chunk's
-    // copy: loads complete in issue order, so the wait for them (after the
-    // product chain) leaves the copy in flight. This wavefront has no
-    // stores outstanding here.
-    StashRaw raw;
-    if constexpr (!FIRST) raw = stash_load<PREC>(stash, stash_at<PREC, WP>(j - 1, rb));
     if (pre) {
       // chunks run layer d, d-1, ..., 2 and blocks 0..RB-1 within a layer
       const int c1 = c + 1;
@@ -438,7 +419,7 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
 #pragma unroll
       for (int e = 0; e < T::NR; ++e) cs[e] = act_slope<ACT>(z[e], act_arg<ACT>(z[e], kf1), kf1);
     } else {
-      stash_unpack<PREC>(raw, cs);
+      stash_get<PREC>(stash, stash_at<PREC, WP>(j - 1, rb), cs);
     }
     bwd_epilogue<PREC, C::KS>((const float*)(slot + C::TAIL_OFF_B), T::BM, g, rb, acc, v0, v1, cs,
                               out, FIRST, w1t, gx);
