@@ -74,24 +74,49 @@ __device__ __forceinline__ typename Tr<PREC>::Acc mma_chain(const char* slot, in
   return acc;
 }
 
+// This lane's position in its wavefront, computed afresh at each use (an asm
+// statement is neither merged with another nor hoisted out of a loop), so
+// that neither it nor the thread index is kept live, or spilled, across the
+// tile loop.
+__device__ __forceinline__ int lane_now() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
+}
+
 // load_chunk from byte src_off (uniform) of a buffer resource: each lane's
-// source is a 32-bit offset formed at the load, so no 64-bit per-lane
-// address stays live between chunks (this kernel's register budget is
-// tighter than the forward kernel's).
-template <int BYTES, int NW>
+// source is a 32-bit offset, so no 64-bit per-lane address stays live
+// between chunks (this kernel's register budget is tighter than the forward
+// kernel's). FRESH: a piece's offset is split into its uniform part
+// (src_off + q KB, a scalar register) and the lane's 16 bytes from
+// lane_now(), so that nothing lane-derived stays live at all; it costs a few
+// vector instructions per copy and pays only where the kernel spills (the
+// FINER 16-bit forms: their per-piece offsets were spilled and reloaded,
+// with a full wait, right after the copy was issued).
+template <int BYTES, int NW, bool FRESH>
 __device__ __forceinline__ void load_chunk_buf(__amdgpu_buffer_rsrc_t src, int src_off, char* dst,
                                                int wave, int lane) {
   constexpr int NP = BYTES / 16;
   constexpr int WL = (NP + 64 * NW - 1) / (64 * NW);
+  if constexpr (FRESH) lane = lane_now();
 #pragma unroll
   for (int k = 0; k < WL; ++k) {
     const int q = k * NW + wave;
     const int piece = q * 64 + lane;
-    if (q * 64 < NP && piece < NP)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(src, lds_ptr(dst + q * 1024), 16, piece * 16,
-                                               src_off, 0, 0);
+    if (q * 64 < NP && piece < NP) {
+      if constexpr (FRESH)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(src, lds_ptr(dst + q * 1024), 16, lane * 16,
+                                                 src_off + q * 1024, 0, 0);
+      else
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(src, lds_ptr(dst + q * 1024), 16, piece * 16,
+                                                 src_off, 0, 0);
+    }
   }
 }
+
+// Whether an instantiation's weight copies use load_chunk_buf's FRESH form.
+template <int PREC, int ACT>
+constexpr bool kFreshCopy = ACT == ACT_FINER && PREC != PREC_FP32;
 
 // Fourth word of a raw buffer resource on gfx9 (32-bit data format).
 constexpr int kBufferWord3 = 0x00020000;
@@ -107,16 +132,6 @@ constexpr int kAdjPF = 4;
 __device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::: "memory"); }
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
-
-// This lane's position in its wavefront, computed afresh at each use (an asm
-// statement is neither merged with another nor hoisted out of a loop), so
-// that neither it nor the thread index is kept live, or spilled, across the
-// tile loop.
-__device__ __forceinline__ int lane_now() {
-  int l;
-  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
-  return l;
-}
 
 // Tr<PREC>::lane_sum with the exchange addresses formed from lane_now()
 // (ds_bpermute reads lane address / 4).
@@ -349,8 +364,8 @@ __device__ __forceinline__ void adj_fwd_layer(float kf, __amdgpu_buffer_rsrc_t h
   for (int rb = 0; rb < C::RB; ++rb) {
     const bool pre = c + 1 < nc;
     if (pre)
-      load_chunk_buf<C::CH, C::NW>(hidden, (c + 1) * C::CH, ring + ((c + 1) & 1) * A::SLOT, wave,
-                                   lane);
+      load_chunk_buf<C::CH, C::NW, kFreshCopy<PREC, ACT>>(
+          hidden, (c + 1) * C::CH, ring + ((c + 1) & 1) * A::SLOT, wave, lane);
     const char* slot = ring + (c & 1) * A::SLOT;
     // bias step first, then the K steps: the forward kernel's order, so the
     // recomputed values are bit-identical to a plain query (the bias tile
@@ -404,8 +419,8 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
       // chunks run layer d, d-1, ..., 2 and blocks 0..RB-1 within a layer
       const int c1 = c + 1;
       const int jn = d - c1 / C::RB, rn = c1 % C::RB;
-      load_chunk_buf<C::CH_B, C::NW>(bwd, ((jn - 2) * C::RB + rn) * C::CH_B,
-                                     ring + (c1 & 1) * A::SLOT, wave, lane);
+      load_chunk_buf<C::CH_B, C::NW, kFreshCopy<PREC, ACT>>(
+          bwd, ((jn - 2) * C::RB + rn) * C::CH_B, ring + (c1 & 1) * A::SLOT, wave, lane);
     }
     const char* slot = ring + (c & 1) * A::SLOT;
     const typename T::Acc acc = mma_chain<PREC, C::KS, kAdjPF>(
@@ -566,7 +581,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     const int nc = (d - 1) * C::RB;
     int c = 0;
     if (nc > 0) {
-      load_chunk_buf<C::CH, C::NW>(hidden, 0, ring, wave, lane);
+      load_chunk_buf<C::CH, C::NW, kFreshCopy<PREC, ACT>>(hidden, 0, ring, wave, lane);
       wait_chunk();
       __syncthreads();
     }
@@ -627,7 +642,8 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     const int ncb = (d - 1) * C::RB;
     c = 0;
     if (ncb > 0) {
-      load_chunk_buf<C::CH_B, C::NW>(bwd, (d - 2) * C::RB * C::CH_B, ring, wave, lane);
+      load_chunk_buf<C::CH_B, C::NW, kFreshCopy<PREC, ACT>>(bwd, (d - 2) * C::RB * C::CH_B, ring,
+                                                            wave, lane);
       wait_chunk();
       __syncthreads();
     }
