@@ -201,6 +201,39 @@ __device__ __forceinline__ void stash_get(const Stash& st, int soff, float (&c)[
   }
 }
 
+// Copy a wavefront's stashed cosines of one block (64 LB bytes from byte
+// soff of its stash) into LDS at dst, without passing through registers,
+// as the weight chunks are copied: the backward requests the next block's
+// cosines with the next weight chunk and reads them from LDS (stash_lds),
+// so their global-memory latency is covered by a block of work.
+template <int PREC>
+__device__ __forceinline__ void stash_fetch(const Stash& st, int soff, char* dst, int lane) {
+  constexpr int SB = 64 * stash_lane_bytes<PREC>();
+#pragma unroll
+  for (int k = 0; k < SB / 1024; ++k)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(st.rsrc, lds_ptr(dst + k * 1024), 16, lane * 16,
+                                             soff + k * 1024, 0, 0);
+}
+
+// The lane's cosines of a block copied by stash_fetch (the stash's own
+// layout: the lane's LB bytes at lane LB).
+template <int PREC>
+__device__ __forceinline__ void stash_lds(const char* src, int lane, float (&c)[Tr<PREC>::NR]) {
+  if constexpr (PREC == PREC_FP32) {
+    const f32x4 v = *(const f32x4*)(src + lane * 16);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = v[k];
+  } else {
+    using V = typename Tr<PREC>::V;
+    const V lo = *(const V*)(src + lane * 32), hi = *(const V*)(src + lane * 32 + 16);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      c[k] = (float)lo[k];
+      c[8 + k] = (float)hi[k];
+    }
+  }
+}
+
 template <int PREC, int KS>
 __device__ __forceinline__ void pin_out(const typename Tr<PREC>::V (&out)[KS], int rb) {
   using T = Tr<PREC>;
@@ -331,7 +364,14 @@ struct AdjCfg {
   static constexpr int SLOT = C::CH > C::CH_B ? C::CH : C::CH_B;
   static constexpr int W1T = WP * 16;
   static constexpr int UST = C::NW * kMaxLayers * Tr<PREC>::NQ * 2 * 4;   // tail factors
-  static constexpr int LDS = 2 * SLOT + C::L1B + W1T + UST;
+  // backward: two blocks of each wavefront's stashed cosines (stash_fetch),
+  // at widths >= 256 only, where one workgroup per CU is the limit anyway
+  // (narrower layers keep two or more workgroups per CU and read the stash
+  // directly)
+  static constexpr bool LSTASH = WP >= 256;
+  static constexpr int SB = 64 * stash_lane_bytes<PREC>();
+  static constexpr int SST = LSTASH ? 2 * C::NW * SB : 0;
+  static constexpr int LDS = 2 * SLOT + C::L1B + W1T + UST + SST;
   // stash bytes per wavefront and layer
   static constexpr int STASH_WL = C::RB * 64 * stash_lane_bytes<PREC>();
 };
@@ -404,7 +444,7 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
                                               const char* l1, float px, float py, float pz,
                                               const typename Tr<PREC>::V (&in)[Cfg<PREC, WP>::KS],
                                               typename Tr<PREC>::V (&out)[Cfg<PREC, WP>::KS],
-                                              const Stash& stash, float v0, float v1,
+                                              const Stash& stash, char* sst, float v0, float v1,
                                               const char* w1t,
                                               float (&gx)[3]) {
   using C = Cfg<PREC, WP>;
@@ -421,6 +461,11 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
       const int jn = d - c1 / C::RB, rn = c1 % C::RB;
       load_chunk_buf<C::CH_B, C::NW, kFreshCopy<PREC, ACT>>(
           bwd, ((jn - 2) * C::RB + rn) * C::CH_B, ring + (c1 & 1) * A::SLOT, wave, lane);
+      // and that block's cosines of layer jn - 1 (none for layer 2, whose
+      // layer-1 cosines are recomputed)
+      if (A::LSTASH && jn >= 3)
+        stash_fetch<PREC>(stash, stash_at<PREC, WP>(jn - 1, rn), sst + (c1 & 1) * C::NW * A::SB,
+                          lane);
     }
     const char* slot = ring + (c & 1) * A::SLOT;
     const typename T::Acc acc = mma_chain<PREC, C::KS, kAdjPF>(
@@ -434,7 +479,10 @@ __device__ __forceinline__ void adj_bwd_layer(float kf1, __amdgpu_buffer_rsrc_t 
 #pragma unroll
       for (int e = 0; e < T::NR; ++e) cs[e] = act_slope<ACT>(z[e], act_arg<ACT>(z[e], kf1), kf1);
     } else {
-      stash_get<PREC>(stash, stash_at<PREC, WP>(j - 1, rb), cs);
+      if constexpr (A::LSTASH)
+        stash_lds<PREC>(sst + (c & 1) * C::NW * A::SB, lane, cs);
+      else
+        stash_get<PREC>(stash, stash_at<PREC, WP>(j - 1, rb), cs);
     }
     bwd_epilogue<PREC, C::KS>((const float*)(slot + C::TAIL_OFF_B), T::BM, g, rb, acc, v0, v1, cs,
                               out, FIRST, w1t, gx);
@@ -485,6 +533,7 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       a.stash + (size_t)blockIdx.x * a.stash_wg + (size_t)wave * L * A::STASH_WL, 0,
       L * A::STASH_WL, kBufferWord3);
   float* uw = ust + wave * kMaxLayers * NQ * 2;   // [layer][point][2]
+  char* sst = (char*)ust + A::UST + wave * A::SB;   // this wavefront's stash ring
 
   // Tiles (deepest first) are drawn one at a time from a counter, so a
   // workgroup that drew deep tiles draws fewer and none ends a whole deep
@@ -642,8 +691,11 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     const int ncb = (d - 1) * C::RB;
     c = 0;
     if (ncb > 0) {
+      // the forward's stash stores have completed before the stash is read
+      wait_chunk();
       load_chunk_buf<C::CH_B, C::NW, kFreshCopy<PREC, ACT>>(bwd, (d - 2) * C::RB * C::CH_B, ring,
                                                             wave, lane);
+      if (A::LSTASH && d >= 3) stash_fetch<PREC>(stash, stash_at<PREC, WP>(d - 1, 0), sst, lane);
       wait_chunk();
       __syncthreads();
     }
@@ -651,12 +703,12 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
     // ends in the input gradient from whichever buffer holds delta'_2
     for (int j = d; j >= 3; j -= 2) {
       adj_bwd_layer<PREC, WP, ACT, false>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, j, l1, px,
-                                          py, pz, actA, actB, stash,
+                                          py, pz, actA, actB, stash, sst,
                                           uw[((j - 2) * NQ + col) * 2],
                                           uw[((j - 2) * NQ + col) * 2 + 1], w1t, gx);
       if (j - 1 < 3) break;
       adj_bwd_layer<PREC, WP, ACT, false>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, j - 1, l1,
-                                          px, py, pz, actB, actA, stash,
+                                          px, py, pz, actB, actA, stash, sst,
                                           uw[((j - 3) * NQ + col) * 2],
                                           uw[((j - 3) * NQ + col) * 2 + 1], w1t, gx);
     }
@@ -665,11 +717,11 @@ __global__ __launch_bounds__((Cfg<PREC, WP>::NT)) void k_adjoint(AdjointArgs a) 
       const f32x4 pt = spt[wave * 64 + lane_now()];
       if (((d - 2) & 1) == 0)
         adj_bwd_layer<PREC, WP, ACT, true>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, 2, l1,
-                                           pt[0], pt[1], pt[2], actA, actB, stash, v0, v1, w1t,
+                                           pt[0], pt[1], pt[2], actA, actB, stash, sst, v0, v1, w1t,
                                            gx);
       else
         adj_bwd_layer<PREC, WP, ACT, true>(q.m.kf[0], bwd, ring, wave, lane, g, c, ncb, d, 2, l1,
-                                           pt[0], pt[1], pt[2], actB, actA, stash, v0, v1, w1t,
+                                           pt[0], pt[1], pt[2], actB, actA, stash, sst, v0, v1, w1t,
                                            gx);
     }
     const float gxs = adj_lane_sum<PREC>(gx[0]), gys = adj_lane_sum<PREC>(gx[1]),
