@@ -118,12 +118,27 @@ def cpu_baseline(blob, dmap, n_sample, target_s=12.0, n_single=1 << 16):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     with threadpool_limits(limits=1):
         dt1 = run(n_single)
-    return {"value": n_sample / dt, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
+    # the small case in full: 4x64 linear-tail model, 32^3 sphere band map,
+    # all 64^3 cell centres
+    m1 = oracle.parse_blob(synth.write_blob(synth.siren_tmlp(1, 4, 64, tails="linear",
+                                                             scale="plain")))
+    dm1, x1 = synth.band_map_c1(32), synth.grid_points(64)
+    t0 = time.perf_counter()
+    oracle.forward(m1, x1, oracle.lookup_depth(x1, dm1, 4))
+    dt_c1 = time.perf_counter() - t0
+    rate = n_sample / dt
+    return {"value": rate, "unit": "queries/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n_sample} uniformly sampled cells of the 512^3 grid, same model and "
                       f"map, FP64 numpy (lookup + adaptive forward), {dt:.1f} s",
             "cpu_model": cpu_model_name(), "host_cpus": os.cpu_count(),
+            "extrapolated_512grid_s": G ** 3 / rate,
+            "extrapolation": "linear in the point count (each query's work is independent)",
             "single_thread": {"value": n_single / dt1, "unit": "queries/s",
-                              "sample": f"{n_single} cells, one BLAS thread, {dt1:.1f} s"}}
+                              "sample": f"{n_single} cells, one BLAS thread, {dt1:.1f} s"},
+            "small_case_full": {"value": x1.shape[0] / dt_c1, "unit": "queries/s",
+                                "sample": f"all {x1.shape[0]} cell centres of the 64^3 grid, "
+                                          f"4x64 linear-tail model, 32^3 sphere band map, "
+                                          f"{dt_c1:.2f} s"}}
 
 
 def valu_estimate(depth_hist, width):
