@@ -63,7 +63,7 @@ def test_grad_8x256_camera_rays(prec):
 
 @pytest.mark.parametrize("W,L,tails", [(16, 1, "mult"), (64, 4, "linear"), (100, 3, "mult"),
                                        (128, 2, "mult"), (336, 5, "mult"), (352, 2, "linear")])
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_grad_shapes(W, L, tails, prec):
     say(f"case: gradient W={W} L={L} {tails} tails {prec}")
     blob = synth.write_blob(synth.siren_tmlp(300 + W, L, W, tails=tails))
