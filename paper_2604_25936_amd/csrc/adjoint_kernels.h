@@ -25,6 +25,10 @@
 //    packed delta_j registers are the B operand as they stand); the
 //    epilogue adds the tail term, multiplies by the stashed cosine and packs
 //    delta_{j-1}; at layer 1 it accumulates dy/dx on the vector ALU instead.
+//    The tile's exit layer keeps its cosines in registers and layer 1's are
+//    recomputed from the point, so only layers 2..d-1 use the stash; at
+//    widths >= 256 each block's cosines are copied into LDS one block ahead,
+//    with the next weight chunk.
 
 #pragma once
 
