@@ -208,7 +208,9 @@ __device__ __forceinline__ void wave_histogram_n(const int (&d)[P], const bool (
 constexpr int kPP = 4;
 constexpr int kQuadRounds = kLookupChunk / (kLookupThreads * kPP);
 
-template <bool DEFER>
+// OCT = false: a dense map only (oct is ignored), so the octree descent's
+// registers do not limit the occupancy of the dense-map lookup.
+template <bool DEFER, bool OCT = true>
 __device__ __forceinline__ void lookup_block(
     int64_t blk, const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
     int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
@@ -262,7 +264,7 @@ __device__ __forceinline__ void lookup_block(
     }
     // the map's depth (and, for an octree, the leaf's value) of every point;
     // FORCED mode keeps the map's far value for points forced to depth 0
-    if (oct != nullptr) {
+    if (OCT && oct != nullptr) {
       if (DEFER)
         octree_leaves<kPP, true>(*oct, x, y, z, d, farv);
       else if (mode != 1)
@@ -355,14 +357,14 @@ __device__ __forceinline__ void lookup_block(
 }
 
 // DEFER: the octree's two-pass adaptive lookup (first pass)
-template <bool DEFER>
+template <bool DEFER, bool OCT>
 __global__ __launch_bounds__(kLookupThreads) void k_lookup_count(
     const float* __restrict__ xyz, int64_t n, const uint8_t* __restrict__ map,
     int R, const float* __restrict__ far, const OctreeArgs* __restrict__ oct,
     const uint8_t* __restrict__ forced, int mode, int L, int max_depth,
     uint8_t* __restrict__ depth, float* __restrict__ sdf, float* __restrict__ grad,
     int32_t* __restrict__ counts, int32_t* __restrict__ queue, int32_t* __restrict__ qcount) {
-  lookup_block<DEFER>(blockIdx.x, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth,
+  lookup_block<DEFER, OCT>(blockIdx.x, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth,
                       sdf, grad, counts, queue, qcount);
 }
 
@@ -702,13 +704,17 @@ hipError_t launch_lookup_count(const float* xyz, int64_t n, const uint8_t* map, 
   const int64_t nblk = (n + kLookupChunk - 1) / kLookupChunk;
   const bool two_pass = oct != nullptr && mode == 0 && queue != nullptr && qcount != nullptr;
   if (two_pass)
-    hipLaunchKernelGGL(k_lookup_count<true>, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s,
-                       xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad,
+    hipLaunchKernelGGL((k_lookup_count<true, true>), dim3((unsigned)nblk), dim3(kLookupThreads), 0,
+                       s, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad,
                        counts, queue, qcount);
-  else
-    hipLaunchKernelGGL(k_lookup_count<false>, dim3((unsigned)nblk), dim3(kLookupThreads), 0, s,
-                       xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad,
+  else if (oct != nullptr)
+    hipLaunchKernelGGL((k_lookup_count<false, true>), dim3((unsigned)nblk), dim3(kLookupThreads), 0,
+                       s, xyz, n, map, R, far, oct, forced, mode, L, max_depth, depth, sdf, grad,
                        counts, nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_lookup_count<false, false>), dim3((unsigned)nblk), dim3(kLookupThreads),
+                       0, s, xyz, n, map, R, far, nullptr, forced, mode, L, max_depth, depth, sdf,
+                       grad, counts, nullptr, nullptr);
   if (two_pass) {
     hipLaunchKernelGGL(k_oct_deferred, dim3((unsigned)nblk), dim3(64), 0, s, xyz, oct,
                        max_depth, queue, qcount, depth, sdf, grad, counts);
