@@ -228,25 +228,30 @@ __device__ __forceinline__ void lookup_block(
   const bool vec_in = ((uintptr_t)xyz & 15) == 0;
   const bool vec_depth = ((uintptr_t)depth & 3) == 0;
   const bool vec_sdf = ((uintptr_t)sdf & 15) == 0;
-  float pt[kQuadRounds][3 * kPP];
-#pragma unroll
-  for (int r = 0; r < kQuadRounds; ++r) {
+  // coordinates of PIPE rounds in flight: all of them with an octree; two
+  // for a dense map, the next but one loaded as each round is taken (fewer
+  // registers, more wavefronts per SIMD)
+  constexpr int PIPE = OCT ? kQuadRounds : 2;
+  float pt[PIPE][3 * kPP];
+  auto load_round = [&](int r, float (&dst)[3 * kPP]) {
     const int64_t q0 = base + ((int64_t)r * kLookupThreads + t) * kPP;
     if (vec_in && q0 + kPP <= n) {
       const float4* src = (const float4*)(xyz + 3 * q0);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const float4 f = src[k];
-        pt[r][4 * k] = f.x;
-        pt[r][4 * k + 1] = f.y;
-        pt[r][4 * k + 2] = f.z;
-        pt[r][4 * k + 3] = f.w;
+        dst[4 * k] = f.x;
+        dst[4 * k + 1] = f.y;
+        dst[4 * k + 2] = f.z;
+        dst[4 * k + 3] = f.w;
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < 3 * kPP; ++k) pt[r][k] = 3 * q0 + k < 3 * n ? xyz[3 * q0 + k] : 0.0f;
+      for (int k = 0; k < 3 * kPP; ++k) dst[k] = 3 * q0 + k < 3 * n ? xyz[3 * q0 + k] : 0.0f;
     }
-  }
+  };
+#pragma unroll
+  for (int r = 0; r < PIPE; ++r) load_round(r, pt[r]);
   __syncthreads();   // hist cleared
 #pragma unroll
   for (int r = 0; r < kQuadRounds; ++r) {
@@ -255,13 +260,14 @@ __device__ __forceinline__ void lookup_block(
     int d[kPP], cell[kPP];
 #pragma unroll
     for (int i = 0; i < kPP; ++i) {
-      x[i] = pt[r][3 * i];
-      y[i] = pt[r][3 * i + 1];
-      z[i] = pt[r][3 * i + 2];
+      x[i] = pt[r % PIPE][3 * i];
+      y[i] = pt[r % PIPE][3 * i + 1];
+      z[i] = pt[r % PIPE][3 * i + 2];
       cell[i] = -1;
       farv[i] = __builtin_nanf("");
       d[i] = 0;
     }
+    if (r + PIPE < kQuadRounds) load_round(r + PIPE, pt[r % PIPE]);
     // the map's depth (and, for an octree, the leaf's value) of every point;
     // FORCED mode keeps the map's far value for points forced to depth 0
     if (OCT && oct != nullptr) {
